@@ -1,0 +1,209 @@
+"""Benchmark: SU(2) checkerboard heat-bath link updates/s on one MI355X.
+
+Default workload (32^4 lattice, beta = 2.6, hot start from Philox seed 2,
+binary32 links with binary64 reductions and reunitarisation norm): one step
+is one heat-bath sweep (8 checkerboard substeps over all 4V links) followed
+by the mean plaquette, run through the batched path (the sweep and its
+measurement captured once in a HIP graph and replayed; batch of one).
+
+Prints ONE JSON line: value = link updates/s of the timed region, the
+roofline of the dominant kernel (the heat-bath substep; algorithmic traffic
+8 link transfers = 128 B per update, timed per launch with HIP events on the
+stream it runs on), the plain FP64 single-lattice form on the same GPU for
+comparison, and the serial FP64 oracle timed on the host cores on a bounded
+sample.
+
+  python bench.py [--steps K] [--warmup W] [--config c2|control64|c3|c5]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def configs():
+    c3 = [(32, 32, 32, 4)] * 16, [2.1 + 0.4 * i / 15 for i in range(16)]
+    combos = [(L, L, L, Nt) for L in (8, 12, 16, 24) for Nt in (4, 6, 8, L)]
+    c5 = [combos[i % 16] for i in range(64)], [2.2 + 0.6 * i / 63 for i in range(64)]
+    return {
+        "c2": dict(dims=[(32, 32, 32, 32)], betas=[2.6], seed=2, poly=False,
+                   desc="32^4 SU(2) heat bath, beta=2.6, hot start, 1 sweep + plaquette per step"),
+        "control64": dict(dims=[(64, 64, 64, 64)], betas=[2.6], seed=2, poly=False,
+                          desc="64^4 SU(2) heat bath (1 GiB of links, beyond the 256 MB "
+                               "Infinity Cache), beta=2.6, 1 sweep + plaquette per step"),
+        "c3": dict(dims=c3[0], betas=c3[1], seed=3, poly=True,
+                   desc="16 x 32^3x4 beta scan [2.1,2.5] in one launch, 1 sweep + plaquette "
+                        "+ Polyakov per step"),
+        "c5": dict(dims=c5[0], betas=c5[1], seed=5, poly=True,
+                   desc="64 uneven lattices L^3xNt, L in {8,12,16,24}, Nt in {4,6,8,L}, "
+                        "beta in [2.2,2.8], 1 sweep + plaquette + Polyakov per step"),
+    }
+
+
+def cpu_baseline(dims, beta, seed, nsweeps):
+    """The serial FP64 oracle on the host: nsweeps sweeps + plaquettes."""
+    from oracle import oracle as orc
+    U = orc.hot(dims, seed)
+    t0 = time.perf_counter()
+    for sw in range(nsweeps):
+        orc.heatbath_sweep(dims, U, beta, seed, sw)
+        orc.plaquette(dims, U)
+    dt = time.perf_counter() - t0
+    V = 1
+    for d in dims:
+        V *= d
+    return 4 * V * nsweeps / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c2", choices=sorted(configs()))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(sharding is described in DESIGN.md)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1010_4834_amd import su2
+
+    cfg = configs()[args.config]
+    dims, betas, seed = cfg["dims"], cfg["betas"], cfg["seed"]
+    n = len(dims)
+    V_tot = sum(int(np.prod(d)) for d in dims)
+    updates_per_step = 4 * V_tot
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    ens = su2.su2_ensemble_create(dims, betas, su2.HOT, seed, su2.F32)
+    su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
+    if not args.no_tune:
+        su2.su2_ensemble_autotune(ens)
+    block, grid, remap = None, None, None
+    su2.su2_ensemble_run(ens, n, args.warmup, seed, True, cfg["poly"])
+
+    # ---- timed region: K steps, graph replay, one D2H of the series ----
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    P, L = su2.su2_ensemble_run(ens, n, args.steps, seed, True, cfg["poly"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    secs = max(wall, gpu_ms * 1e-3)
+    value = updates_per_step * args.steps / secs
+    assert np.isfinite(P).all() and (P > 0).all() and (P < 1).all(), "plaquette series invalid"
+
+    # ---- dominant kernel: every heat-bath launch bracketed by HIP events ----
+    su2.su2_ensemble_set_timing(ens, 1)
+    su2.su2_ensemble_run(ens, n, args.steps, seed, True, cfg["poly"])
+    hb_ms, hb_n = su2.su2_ensemble_get_timing(ens, su2.K_HEATBATH)
+    pl_ms, pl_n = su2.su2_ensemble_get_timing(ens, su2.K_PLAQUETTE)
+    su2.su2_ensemble_set_timing(ens, 0)
+    hb_avg_us = 1e3 * hb_ms / hb_n
+    link_b = 16
+    hb_bytes = (updates_per_step // 8) * 8 * link_b   # per substep: V/2 updates x 128 B
+    achieved = hb_bytes / (hb_avg_us * 1e-6) / 1e9
+    pl_avg_us = 1e3 * pl_ms / max(pl_n, 1)
+    pl_bytes = 4 * V_tot * link_b
+    tries, updates = su2.su2_ensemble_stats(ens)
+    su2.su2_ensemble_destroy(ens)
+
+    out = {
+        "metric": "heat-bath link updates/s + HBM GB/s fraction, FP32 batched vs FP64 at 32^4",
+        "value": value,
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Philox hot start)",
+        "config": {"workload": cfg["desc"], "lattices": n, "sites": V_tot,
+                   "links": "binary32, binary64 reductions and norm", "sweeps_per_step": 1,
+                   "sampler": "Kennedy-Pendleton (alpha>=2) / Creutz"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_heatbath<float> (one checkerboard substep)",
+                     "bytes_per_launch": hb_bytes, "avg_launch_us": hb_avg_us},
+        "plaquette_kernel": {"avg_launch_us": pl_avg_us,
+                             "GBs": pl_bytes / (pl_avg_us * 1e-6) / 1e9},
+        "effective_GBs_step": updates_per_step * 9 * link_b / (1e-3 * 1e3 * secs / args.steps) / 1e9,
+        "tries_per_update": tries / max(updates, 1),
+        "gpu_event_ms": gpu_ms,
+    }
+
+    # ---- the plain FP64 single-lattice form on the same GPU ----
+    if not args.no_fp64 and n == 1:
+        lat = su2.su2_create(*dims[0], su2.HOT, seed, su2.F64)
+        su2.su2_set_stream(lat, stream.cuda_stream)
+        su2.su2_heatbath(lat, betas[0], 5, seed)
+        su2.su2_plaquette(lat)
+        k64 = max(10, args.steps // 4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            su2.su2_heatbath(lat, betas[0], 1, seed)
+            su2.su2_plaquette(lat)
+        torch.cuda.synchronize()
+        s64 = time.perf_counter() - t0
+        su2.su2_set_timing(lat, 1)
+        for _ in range(k64):
+            su2.su2_heatbath(lat, betas[0], 1, seed)
+        hb64_ms, hb64_n = su2.su2_get_timing(lat, su2.K_HEATBATH)
+        su2.su2_destroy(lat)
+        v64 = updates_per_step * k64 / s64
+        hb64_us = 1e3 * hb64_ms / hb64_n
+        out["fp64_plain"] = {"value": v64, "ms_per_step": 1e3 * s64 / k64, "steps": k64,
+                             "hb_avg_launch_us": hb64_us,
+                             "hb_GBs": (updates_per_step // 8) * 256 / (hb64_us * 1e-6) / 1e9,
+                             "speedup_fp32_batched": value / v64}
+
+    if args.copy_probe:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            y.copy_(x)
+        c1.record()
+        torch.cuda.synchronize()
+        out["copy_probe_GBs"] = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        del x, y
+
+    if not args.no_cpu_baseline and args.config == "c2":
+        rate, dt = cpu_baseline(dims[0], betas[0], seed, args.cpu_sweeps)
+        out["cpu_baseline"] = {"value": rate, "unit": "link updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{args.cpu_sweeps} heat-bath sweeps + plaquette of the "
+                                         f"32^4 beta=2.6 hot-start lattice, serial FP64 oracle, "
+                                         f"{dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

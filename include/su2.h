@@ -1,0 +1,231 @@
+/*
+ * su2.h -- C ABI of the MI355X (gfx950) SU(2) lattice gauge Monte Carlo
+ * library: checkerboard heat-bath sweeps of the Wilson action and the
+ * measurements they feed.
+ *
+ * Method: N. Cardoso, P. Bicudo, "SU(2) Lattice Gauge Theory Simulations on
+ * Fermi GPUs", arXiv:1010.4834.  Each call below names the section or
+ * equation of the paper that defines what it computes.
+ *
+ * Conventions shared by every call
+ *  - Every call returns su2_status (SU2_OK = 0); nothing aborts or throws
+ *    across the ABI.  After SU2_EDEVICE the handle is failed and every later
+ *    call on it returns SU2_ESTATE (su2_destroy excepted).
+ *  - Lattice extents Nx, Ny, Nz, Nt are even and >= 2 (the even/odd
+ *    checkerboard of a periodic lattice needs even extents).  mu = 0,1,2 are
+ *    x,y,z and mu = 3 is time (the paper's U_4).
+ *  - Host link arrays use the canonical layout: site s = x + Nx*(y + Ny*(z +
+ *    Nz*t)), element [(s*4 + mu)*4 + c] with c = 0..3 the components
+ *    (a0, a1, a2, a3) of U = a0 1 + i a.sigma (paper Sec. 2), in float64.
+ *    Host pointers are borrowed for the duration of the call only; output
+ *    arrays are sized by the caller.
+ *  - Device memory (the link buffer, smeared links, Wilson lines, reduction
+ *    partials) is owned by the handle unless the caller passes its own link
+ *    buffer to su2_create / su2_ensemble_create, which must then outlive the
+ *    handle.  Calls are asynchronous on the handle's stream except those that
+ *    return host results, which synchronise that stream.
+ *  - A handle is not thread-safe; separate handles are independent.
+ *  - Precision SU2_F32 keeps links in binary32 and does every global
+ *    reduction and the reunitarisation norm in binary64 (compensated
+ *    two-sum accumulation); SU2_F64 is binary64 throughout.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
+ *    counter = (site, sweep, lattice_id<<8 | purpose<<4 | mu<<1 | parity,
+ *    try).  One heat-bath sweep consumes the counters of one sweep index;
+ *    each lattice keeps a sweep counter so successive calls continue the
+ *    stream.  Results do not depend on launch shapes.
+ */
+#ifndef SU2_H
+#define SU2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct su2_lattice_s *su2_lattice;   /* one lattice */
+typedef struct su2_ensemble_s *su2_ensemble; /* independent lattices, one launch */
+
+typedef enum {
+    SU2_OK = 0,
+    SU2_EINVAL = -1,   /* invalid argument                                  */
+    SU2_ENOMEM = -2,   /* device or host allocation failed                  */
+    SU2_ENODEV = -3,   /* no usable GPU                                     */
+    SU2_EDEVICE = -4,  /* a HIP call failed; the handle is now failed       */
+    SU2_ESTATE = -5,   /* handle previously failed, or call out of sequence */
+    SU2_EIO = -6,      /* file I/O or format error                          */
+    SU2_ENUMERIC = -7  /* non-finite value or sampler failure detected      */
+} su2_status;
+
+typedef enum { SU2_COLD = 0, SU2_HOT = 1 } su2_start;
+typedef enum { SU2_F64 = 0, SU2_F32 = 1 } su2_prec;
+/* SU2_HYBRID: Kennedy-Pendleton for alpha = beta*k >= 2, Creutz below it;
+ * SU2_CREUTZ: Creutz for every alpha.  Both are exact samplers of the a0
+ * law of paper Sec. 2. */
+typedef enum { SU2_HYBRID = 0, SU2_CREUTZ = 1 } su2_sampler;
+
+/* Kernel classes for su2_get_timing. */
+typedef enum {
+    SU2_K_HEATBATH = 0, /* one (mu, parity) heat-bath substep        */
+    SU2_K_OVERRELAX = 1,
+    SU2_K_PLAQUETTE = 2,
+    SU2_K_POLYAKOV = 3,
+    SU2_K_REDUCE = 4,   /* final per-lattice reductions           */
+    SU2_K_APE = 5,
+    SU2_K_WILSON = 6,
+    SU2_K_COUNT = 7
+} su2_kernel_kind;
+
+/* Human-readable name of a status code (static storage). */
+const char *su2_status_str(su2_status st);
+
+/* Bytes of the native device link buffer of one lattice: 4*V links of 16 B
+ * (F32) or 32 B (F64).  Returns 0 for invalid extents. */
+size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec);
+
+/* ---- one lattice ------------------------------------------------------ */
+
+/* Allocate a lattice and initialise it (paper Sec. 4 kernel list: cold start
+ * U = 1, hot start a Haar-random SU(2) element per link, Haar measure of
+ * Sec. 2).  The hot start draws Philox purpose 1 with `seed`.
+ * device_links: optional caller-owned device buffer of su2_link_bytes()
+ * bytes (NULL: the library allocates).  EINVAL on odd or < 2 extents, a
+ * volume above 2^31 sites, or a bad enum; ENODEV without a GPU. */
+su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t seed,
+                      su2_prec prec, void *device_links, size_t device_bytes,
+                      su2_lattice *out);
+su2_status su2_destroy(su2_lattice lat);
+
+/* Run later work on this HIP stream (a hipStream_t; NULL = the library's
+ * own stream). */
+su2_status su2_set_stream(su2_lattice lat, void *hip_stream);
+su2_status su2_set_sampler(su2_lattice lat, su2_sampler sampler);
+
+/* nsweeps heat-bath sweeps (paper Sec. 2: each link drawn from
+ * exp(beta/2 Tr(U V)), V the staple, via a0 ~ sqrt(1-a0^2) exp(beta k a0)
+ * and a random direction; paper Sec. 4: chessboard order, separately by
+ * direction and parity).  A sweep is mu = 0..3, even then odd.  The updated
+ * link is renormalised with a binary64 norm.  beta >= 0 and finite,
+ * nsweeps >= 0, else EINVAL.  ENUMERIC if a sampler hit its try cap
+ * (non-finite links). */
+su2_status su2_heatbath(su2_lattice lat, double beta, int nsweeps, uint64_t seed);
+
+/* A single (mu, parity) heat-bath substep with sweep index = the current
+ * counter; the counter is not advanced (custom schedules, parity tests). */
+su2_status su2_heatbath_substep(su2_lattice lat, double beta, uint64_t seed, int mu,
+                                int parity);
+
+/* nsweeps over-relaxation sweeps (paper Sec. 2, over-relaxation equation):
+ * U -> W^dag U^dag W^dag with W = V/sqrt(det V), which keeps Tr(U V); same
+ * chessboard order; no random numbers; the sweep counter is not advanced. */
+su2_status su2_overrelax(su2_lattice lat, int nsweeps);
+
+/* Mean plaquette (paper Sec. 2, eq. for <P>): 1/2 Re Tr of the oriented
+ * plaquette, averaged over the 6V plaquettes (cold start: exactly 1).
+ * spatial / temporal: the averages over the 3V planes with nu < 3 / nu = 3.
+ * Pointers may be NULL.  Synchronises. */
+su2_status su2_plaquette(su2_lattice lat, double *avg, double *spatial, double *temporal);
+
+/* Polyakov loop (paper Sec. 2): (1/N_sigma) sum over spatial sites of
+ * 1/2 Tr prod_{t=0}^{Nt-1} U_4(x,t).  Signed, per configuration.
+ * Synchronises. */
+su2_status su2_polyakov(su2_lattice lat, double *avg);
+
+/* APE smearing of the spatial links (paper Sec. 2, APE equation): nsteps
+ * Jacobi steps U' = P_SU(2)[(1-alpha) U + (alpha/4) sum of the four spatial
+ * staples], into a separate smeared-link buffer; the Markov chain is not
+ * touched.  0 <= alpha <= 1, nsteps >= 0.  The buffer is dropped by the next
+ * update of the links. */
+su2_status su2_ape_smear(su2_lattice lat, double alpha, int nsteps);
+
+/* On-axis Wilson loops (paper Sec. 2, W(R,T)): out[(R-1)*Tmax + (T-1)] for
+ * 1 <= R <= Rmax, 1 <= T <= Tmax, half trace averaged over all sites and the
+ * three spatial directions.  Spatial lines use the smeared links when
+ * su2_ape_smear produced them since the last update, else the raw links.
+ * Rmax <= min(Nx,Ny,Nz), Tmax <= min(Nt, 32), else EINVAL.  Synchronises. */
+su2_status su2_wilson_loops(su2_lattice lat, int Rmax, int Tmax, double *out);
+
+/* Copy links to / from a host array in the canonical layout (V*16 float64).
+ * set rounds to binary32 for SU2_F32 lattices and rejects non-finite values
+ * or links with |1 - |U|^2| > 1e-6 (EINVAL). */
+su2_status su2_get_links(su2_lattice lat, double *host);
+su2_status su2_set_links(su2_lattice lat, const double *host);
+/* Smeared spatial links [s][mu<3][4] float64 (ESTATE if none). */
+su2_status su2_get_smeared(su2_lattice lat, double *host);
+
+/* Native device link buffer: [mu][parity][site/2] per lattice; F32 links are
+ * float4, F64 links two float64x2 planes (a0,a1) and (a2,a3) per
+ * (mu, parity) block. */
+su2_status su2_device_links(su2_lattice lat, void **device_ptr, size_t *bytes);
+
+/* Sweep counter (the Philox sweep word of the next sweep). */
+su2_status su2_get_sweep(su2_lattice lat, uint32_t *sweep);
+su2_status su2_set_sweep(su2_lattice lat, uint32_t sweep);
+
+/* Cumulative heat-bath tries and updates, and the largest |1 - |U|^2| over
+ * the current links.  Any pointer may be NULL.  Synchronises. */
+su2_status su2_stats(su2_lattice lat, uint64_t *tries, uint64_t *updates,
+                     double *max_unit_defect);
+
+/* Per-link try record of later heat-bath calls: tries | creutz << 31 in
+ * canonical [s][mu] order (V*4 uint32).  enable = 0 frees it. */
+su2_status su2_trace_tries(su2_lattice lat, int enable);
+su2_status su2_get_tries(su2_lattice lat, uint32_t *host);
+
+/* Checkpoint: header (magic, version, extents, precision, sweep counter)
+ * and the links in canonical float64.  A resumed run is bitwise identical
+ * to an uninterrupted one (the random stream is counter based). */
+su2_status su2_save(su2_lattice lat, const char *path);
+su2_status su2_load(const char *path, su2_lattice *out);
+
+/* Launch shape: threads per workgroup (64, 128, 192 or 256), resident
+ * workgroups of the persistent grid (0 = one workgroup per tile) and
+ * whether tiles are laid out per XCD (1) or round-robin (0).  Results do
+ * not depend on it. */
+su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap);
+su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap);
+/* Time the candidate launch shapes on this lattice and keep the fastest
+ * (the links are saved and restored around the trial sweeps). */
+su2_status su2_autotune(su2_lattice lat, double beta);
+
+/* Per-kernel timing with HIP events on the handle's stream (enable = 1
+ * also disables graph replay so every kernel is bracketed).  get_timing
+ * returns the summed milliseconds and launch count since enabling. */
+su2_status su2_set_timing(su2_lattice lat, int enable);
+su2_status su2_get_timing(su2_lattice lat, su2_kernel_kind kind, double *ms, int64_t *launches);
+
+/* ---- ensembles of independent lattices -------------------------------- */
+
+/* n independent lattices of uneven sizes and couplings that advance in the
+ * same kernel launches (one workgroup walks a (lattice, tile) list).
+ * dims: n*4 extents; betas: n couplings; lattice i uses lattice_id i in the
+ * Philox counter; hot starts draw with `seed`. */
+su2_status su2_ensemble_create(int n, const int *dims, const double *betas, su2_start start,
+                               uint64_t seed, su2_prec prec, void *device_links,
+                               size_t device_bytes, su2_ensemble *out);
+su2_status su2_ensemble_destroy(su2_ensemble ens);
+su2_status su2_ensemble_set_stream(su2_ensemble ens, void *hip_stream);
+su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
+
+/* nsweeps heat-bath sweeps of every lattice at its own beta, with the mean
+ * plaquette and Polyakov loop of every lattice after every sweep written to
+ * plaq[i*nsweeps + k] and poly[i*nsweeps + k] (either may be NULL to skip
+ * that measurement).  One sweep plus its measurements is captured once in a
+ * HIP graph and replayed; the series stay on the device until the end. */
+su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, uint64_t seed, double *plaq,
+                            double *poly);
+su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
+su2_status su2_ensemble_set_links(su2_ensemble ens, int i, const double *host);
+su2_status su2_ensemble_stats(su2_ensemble ens, uint64_t *tries, uint64_t *updates);
+su2_status su2_ensemble_set_launch(su2_ensemble ens, int block, int grid, int xcd_remap);
+su2_status su2_ensemble_autotune(su2_ensemble ens);
+su2_status su2_ensemble_set_timing(su2_ensemble ens, int enable);
+su2_status su2_ensemble_get_timing(su2_ensemble ens, su2_kernel_kind kind, double *ms,
+                                   int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SU2_H */

@@ -46,6 +46,7 @@ def lib():
             "or_polyakov": (D, [P, P]),
             "or_ape": (None, [P, P, D, C.c_int, P]),
             "or_wilson": (None, [P, P, P, C.c_int, C.c_int, P]),
+            "or_wilson_rt": (D, [P, P, P, C.c_int, C.c_int]),
             "or_gauge_transform": (None, [P, P, U64]),
             "or_max_unit_defect": (D, [P, P]),
         }
@@ -192,6 +193,12 @@ def wilson(n, U, Rmax, Tmax, S=None):
         S = np.ascontiguousarray(S, dtype=np.float64)
     lib().or_wilson(_p(_dims(n)), _p(_links(U)), _p(S), int(Rmax), int(Tmax), _p(W))
     return W
+
+
+def wilson_rt(n, U, R, T, S=None):
+    if S is not None:
+        S = np.ascontiguousarray(S, dtype=np.float64)
+    return lib().or_wilson_rt(_p(_dims(n)), _p(_links(U)), _p(S), int(R), int(T))
 
 
 def gauge_transform(n, U, seed):

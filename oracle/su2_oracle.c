@@ -475,39 +475,43 @@ void or_ape(const int n[4], const double *U, double alpha, int nsteps, double *S
  * from x + T t, the temporal line back to x.  Half trace, averaged over all
  * sites and the three spatial directions (W(1,1) is then the mean
  * spatial-temporal plaquette). */
+double or_wilson_rt(const int n[4], const double *U, const double *S, int R, int T)
+{
+    int64_t V = or_volume(n);
+    or_acc acc = {0, 0};
+    for (int64_t s = 0; s < V; ++s)
+        for (int mu = 0; mu < 3; ++mu) {
+            double L[4] = {1, 0, 0, 0}, t[4], d[4];
+            int64_t y = s;
+            for (int i = 0; i < R; ++i) { /* S_mu(x; R) */
+                const double *u = S ? S + (y * 3 + mu) * 4 : or_clink(U, y, mu);
+                or_qmul(L, u, t); or_set(L, t);
+                y = or_neighbor(n, y, mu, +1);
+            }
+            for (int j = 0; j < T; ++j) { /* T(x + R mu; T) */
+                or_qmul(L, or_clink(U, y, 3), t); or_set(L, t);
+                y = or_neighbor(n, y, 3, +1);
+            }
+            for (int i = 0; i < R; ++i) { /* back along -mu */
+                y = or_neighbor(n, y, mu, -1);
+                const double *u = S ? S + (y * 3 + mu) * 4 : or_clink(U, y, mu);
+                or_dag(u, d); or_qmul(L, d, t); or_set(L, t);
+            }
+            for (int j = 0; j < T; ++j) { /* back along -t */
+                y = or_neighbor(n, y, 3, -1);
+                or_dag(or_clink(U, y, 3), d); or_qmul(L, d, t); or_set(L, t);
+            }
+            or_acc_add(&acc, L[0]);
+        }
+    return or_acc_get(&acc) / (3.0 * (double)V);
+}
+
 void or_wilson(const int n[4], const double *U, const double *S, int Rmax,
                int Tmax, double *W)
 {
-    int64_t V = or_volume(n);
     for (int R = 1; R <= Rmax; ++R)
-        for (int T = 1; T <= Tmax; ++T) {
-            or_acc acc = {0, 0};
-            for (int64_t s = 0; s < V; ++s)
-                for (int mu = 0; mu < 3; ++mu) {
-                    double L[4] = {1, 0, 0, 0}, t[4], d[4];
-                    int64_t y = s;
-                    for (int i = 0; i < R; ++i) { /* S_mu(x; R) */
-                        const double *u = S ? S + (y * 3 + mu) * 4 : or_clink(U, y, mu);
-                        or_qmul(L, u, t); or_set(L, t);
-                        y = or_neighbor(n, y, mu, +1);
-                    }
-                    for (int j = 0; j < T; ++j) { /* T(x + R mu; T) */
-                        or_qmul(L, or_clink(U, y, 3), t); or_set(L, t);
-                        y = or_neighbor(n, y, 3, +1);
-                    }
-                    for (int i = 0; i < R; ++i) { /* back along -mu */
-                        y = or_neighbor(n, y, mu, -1);
-                        const double *u = S ? S + (y * 3 + mu) * 4 : or_clink(U, y, mu);
-                        or_dag(u, d); or_qmul(L, d, t); or_set(L, t);
-                    }
-                    for (int j = 0; j < T; ++j) { /* back along -t */
-                        y = or_neighbor(n, y, 3, -1);
-                        or_dag(or_clink(U, y, 3), d); or_qmul(L, d, t); or_set(L, t);
-                    }
-                    or_acc_add(&acc, L[0]);
-                }
-            W[(R - 1) * Tmax + (T - 1)] = or_acc_get(&acc) / (3.0 * (double)V);
-        }
+        for (int T = 1; T <= Tmax; ++T)
+            W[(R - 1) * Tmax + (T - 1)] = or_wilson_rt(n, U, S, R, T);
 }
 
 /* Gauge transformation with a Haar-random g(x) per site (purpose 2). */

@@ -109,6 +109,9 @@ void or_ape(const int n[4], const double *U, double alpha, int nsteps, double *S
 void or_wilson(const int n[4], const double *U, const double *S, int Rmax,
                int Tmax, double *W);
 
+/* the single loop W(R,T) of or_wilson (sampled checks at large sizes) */
+double or_wilson_rt(const int n[4], const double *U, const double *S, int R, int T);
+
 /* random gauge transformation U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag */
 void or_gauge_transform(const int n[4], double *U, uint64_t seed);
 

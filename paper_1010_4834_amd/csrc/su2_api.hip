@@ -1,0 +1,1124 @@
+// su2_api.hip -- C ABI of the SU(2) library (include/su2.h): handles,
+// validation, device memory, tile tables, graph capture of one sweep,
+// per-kernel event timing, launch-shape autotuning and checkpoints.
+//
+// A lattice is an ensemble of one: every kernel walks the (lattice, tile)
+// list of its handle, so the batched and the single-lattice paths are the
+// same kernels.
+#include "su2_internal.hpp"
+
+#include "../../include/su2.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using su2::DevState;
+using su2::KArgs;
+using su2::LatDesc;
+using su2::Tile;
+
+namespace {
+
+constexpr int NMEAS_GRAPHS = 4;  // measurement mask 0..3 (bit 0 plaquette, bit 1 Polyakov)
+constexpr long long MAX_SITES = 1LL << 30;
+
+struct EventPair {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct su2_ensemble_s {
+    int n = 0;
+    bool f32 = true;
+    int sampler = 0;
+    int device = 0;
+    bool failed = false;
+
+    std::vector<LatDesc> hdesc;
+    LatDesc *ddesc = nullptr;
+    long long total_links = 0;  // 4 * sum V
+    long long total_sites = 0;
+
+    int block = 256, grid = 0, remap = 1;
+    std::vector<Tile> htiles, hstiles, hvtiles;
+    Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr;
+    int ntiles = 0, nstiles = 0, nvtiles = 0;
+
+    void *links = nullptr;
+    bool own_links = true;
+    size_t link_bytes = 0;
+
+    DevState *st = nullptr;
+    DevState hst{};
+    unsigned long long *tries_part = nullptr;
+    unsigned long long tries_acc = 0;  // folded from tries_part on reshapes
+    unsigned long long updates = 0;
+
+    double *part_plaq = nullptr, *part_poly = nullptr;
+    double *res = nullptr;   // device scratch for single results
+    double *hres = nullptr;  // pinned host mirror of res
+    double *ser_plaq = nullptr, *ser_poly = nullptr;
+    int ser_cap = 0;
+
+    hipStream_t own = nullptr, user = nullptr;
+    hipGraphExec_t gexec[NMEAS_GRAPHS] = {};
+
+    void *sm[2] = {nullptr, nullptr};
+    int sm_cur = -1;  // index of the valid smeared buffer, -1 none
+
+    void *wl_t = nullptr, *wl_s = nullptr;
+    size_t wl_t_bytes = 0, wl_s_bytes = 0;
+    double *wpart = nullptr;
+    size_t wpart_bytes = 0;
+
+    uint32_t *trace = nullptr;
+
+    bool timing = false;
+    std::vector<EventPair> pending;
+    std::vector<hipEvent_t> evpool;
+    double tms[SU2_K_COUNT] = {};
+    long long tcount[SU2_K_COUNT] = {};
+
+    hipStream_t stream() const { return user ? user : own; }
+};
+
+struct su2_lattice_s : su2_ensemble_s {};
+
+namespace {
+
+#define HIPCHK(expr)                                  \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) {                       \
+            E->failed = true;                         \
+            if (std::getenv("SU2_LOG"))               \
+                std::fprintf(stderr, "su2: %s failed: %s (%s:%d)\n", #expr, \
+                             hipGetErrorString(e_), __FILE__, __LINE__); \
+            return SU2_EDEVICE;                       \
+        }                                             \
+    } while (0)
+
+#define CHK(st_expr)                   \
+    do {                               \
+        su2_status s_ = (st_expr);     \
+        if (s_ != SU2_OK) return s_;   \
+    } while (0)
+
+size_t link_size(bool f32) { return f32 ? 16 : 32; }
+
+bool dims_ok(const int *d) {
+    for (int k = 0; k < 4; ++k)
+        if (d[k] < 2 || (d[k] & 1)) return false;
+    long long V = (long long)d[0] * d[1] * d[2] * d[3];
+    return V <= MAX_SITES;
+}
+
+su2_status enter(su2_ensemble_s *E) {
+    if (!E) return SU2_EINVAL;
+    if (E->failed) return SU2_ESTATE;
+    if (hipSetDevice(E->device) != hipSuccess) {
+        E->failed = true;
+        return SU2_EDEVICE;
+    }
+    return SU2_OK;
+}
+
+template <class P>
+su2_status dalloc(su2_ensemble_s *E, P **p, size_t bytes) {
+    if (*p) {
+        if (hipFree(*p) != hipSuccess) { E->failed = true; return SU2_EDEVICE; }
+        *p = nullptr;
+    }
+    if (bytes == 0) return SU2_OK;
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return SU2_ENOMEM;
+    }
+    if (e != hipSuccess) { E->failed = true; return SU2_EDEVICE; }
+    return SU2_OK;
+}
+
+KArgs kargs(su2_ensemble_s *E, int which = 0) {
+    KArgs a;
+    a.desc = E->ddesc;
+    a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : E->vtiles;
+    a.ntiles = which == 0 ? E->ntiles : which == 1 ? E->nstiles : E->nvtiles;
+    a.xcd_remap = E->remap;
+    a.links = E->links;
+    a.st = E->st;
+    a.trace = E->trace;
+    a.tries_part = E->tries_part;
+    a.sampler = E->sampler;
+    return a;
+}
+
+void drop_graphs(su2_ensemble_s *E) {
+    for (auto &g : E->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// ---- per-kernel event timing -------------------------------------------
+hipEvent_t take_event(su2_ensemble_s *E) {
+    if (!E->evpool.empty()) {
+        hipEvent_t e = E->evpool.back();
+        E->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timed {
+    su2_ensemble_s *E;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(su2_ensemble_s *e, int k, hipStream_t s) : E(e), kind(k) {
+        if (E->timing) {
+            a = take_event(E);
+            b = take_event(E);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    void done(hipStream_t s) {
+        if (E->timing && a && b) {
+            (void)hipEventRecord(b, s);
+            E->pending.push_back(EventPair{kind, a, b});
+        }
+    }
+};
+
+su2_status collect_timing(su2_ensemble_s *E) {
+    for (auto &p : E->pending) {
+        HIPCHK(hipEventSynchronize(p.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+        E->tms[p.kind] += ms;
+        E->tcount[p.kind] += 1;
+        E->evpool.push_back(p.a);
+        E->evpool.push_back(p.b);
+    }
+    E->pending.clear();
+    return SU2_OK;
+}
+
+// ---- tile tables ----------------------------------------------------------
+su2_status upload_desc(su2_ensemble_s *E) {
+    HIPCHK(hipMemcpyAsync(E->ddesc, E->hdesc.data(), sizeof(LatDesc) * E->n, hipMemcpyHostToDevice,
+                          E->stream()));
+    return SU2_OK;
+}
+
+su2_status fold_tries(su2_ensemble_s *E) {
+    if (!E->tries_part || E->ntiles == 0) return SU2_OK;
+    std::vector<unsigned long long> h(E->ntiles);
+    HIPCHK(hipMemcpyAsync(h.data(), E->tries_part, sizeof(unsigned long long) * E->ntiles,
+                          hipMemcpyDeviceToHost, E->stream()));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    for (auto v : h) E->tries_acc += v;
+    HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, E->stream()));
+    return SU2_OK;
+}
+
+su2_status build_tiles(su2_ensemble_s *E) {
+    CHK(fold_tries(E));
+    E->htiles.clear();
+    E->hstiles.clear();
+    E->hvtiles.clear();
+    const int B = E->block;
+    for (int l = 0; l < E->n; ++l) {
+        LatDesc &d = E->hdesc[l];
+        d.tile0 = (int)E->htiles.size();
+        for (int s = 0; s < d.vh; s += B) E->htiles.push_back(make_int2(l, s));
+        d.ntile = (int)E->htiles.size() - d.tile0;
+        d.stile0 = (int)E->hstiles.size();
+        for (int s = 0; s < d.ns; s += B) E->hstiles.push_back(make_int2(l, s));
+        d.nstile = (int)E->hstiles.size() - d.stile0;
+        d.vtile0 = (int)E->hvtiles.size();
+        for (int s = 0; s < 2 * d.vh; s += B) E->hvtiles.push_back(make_int2(l, s));
+        d.nvtile = (int)E->hvtiles.size() - d.vtile0;
+    }
+    E->ntiles = (int)E->htiles.size();
+    E->nstiles = (int)E->hstiles.size();
+    E->nvtiles = (int)E->hvtiles.size();
+    CHK(dalloc(E, &E->tiles, sizeof(Tile) * E->ntiles));
+    CHK(dalloc(E, &E->stiles, sizeof(Tile) * E->nstiles));
+    CHK(dalloc(E, &E->vtiles, sizeof(Tile) * E->nvtiles));
+    CHK(dalloc(E, &E->tries_part, sizeof(unsigned long long) * E->ntiles));
+    CHK(dalloc(E, &E->part_plaq, sizeof(double) * 4 * E->ntiles));
+    CHK(dalloc(E, &E->part_poly, sizeof(double) * 2 * E->nstiles));
+    HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, E->stream()));
+    HIPCHK(hipMemcpyAsync(E->tiles, E->htiles.data(), sizeof(Tile) * E->ntiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    HIPCHK(hipMemcpyAsync(E->stiles, E->hstiles.data(), sizeof(Tile) * E->nstiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    HIPCHK(hipMemcpyAsync(E->vtiles, E->hvtiles.data(), sizeof(Tile) * E->nvtiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    CHK(upload_desc(E));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    drop_graphs(E);
+    return SU2_OK;
+}
+
+// upload seed / sweep / run_base (not the device-written error word)
+su2_status upload_state(su2_ensemble_s *E) {
+    HIPCHK(hipMemcpyAsync(E->st, &E->hst, offsetof(DevState, err), hipMemcpyHostToDevice, E->stream()));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    return SU2_OK;
+}
+
+su2_status check_err(su2_ensemble_s *E) {
+    unsigned int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, &E->st->err, sizeof(err), hipMemcpyDeviceToHost, E->stream()));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    return err ? SU2_ENUMERIC : SU2_OK;
+}
+
+void invalidate_measure_buffers(su2_ensemble_s *E) { E->sm_cur = -1; }
+
+// ---- creation ----------------------------------------------------------------
+su2_status create_common(int n, const int *dims, const double *betas, su2_start start, uint64_t seed,
+                         su2_prec prec, void *device_links, size_t device_bytes, su2_ensemble_s *E) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return SU2_ENODEV;
+    }
+    if (hipGetDevice(&E->device) != hipSuccess) return SU2_ENODEV;
+    E->n = n;
+    E->f32 = (prec == SU2_F32);
+    E->hdesc.resize(n);
+    long long off = 0, sites = 0;
+    for (int l = 0; l < n; ++l) {
+        const int *d = dims + 4 * l;
+        LatDesc &D = E->hdesc[l];
+        std::memset(&D, 0, sizeof(D));
+        for (int k = 0; k < 4; ++k) D.n[k] = d[k];
+        const long long V = (long long)d[0] * d[1] * d[2] * d[3];
+        D.hx = d[0] / 2;
+        D.vh = (int)(V / 2);
+        D.ns = d[0] * d[1] * d[2];
+        D.lat_id = l;
+        D.off = off;
+        D.soff = 3 * sites;
+        D.toff = off;
+        D.inv_hx = 1.0 / D.hx;
+        D.inv_nx = 1.0 / d[0];
+        D.inv_ny = 1.0 / d[1];
+        D.inv_nz = 1.0 / d[2];
+        D.beta = betas ? betas[l] : 0.0;
+        D.betaf = (float)D.beta;
+        off += 4 * V;
+        sites += V;
+    }
+    E->total_links = off;
+    E->total_sites = sites;
+    E->link_bytes = (size_t)off * link_size(E->f32);
+    if (hipStreamCreateWithFlags(&E->own, hipStreamNonBlocking) != hipSuccess) return SU2_EDEVICE;
+    if (device_links) {
+        if (device_bytes < E->link_bytes) return SU2_EINVAL;
+        E->links = device_links;
+        E->own_links = false;
+    } else {
+        CHK(dalloc(E, &E->links, E->link_bytes));
+    }
+    CHK(dalloc(E, &E->ddesc, sizeof(LatDesc) * n));
+    CHK(dalloc(E, &E->st, sizeof(DevState)));
+    CHK(dalloc(E, &E->res, sizeof(double) * 4 * n));
+    if (hipHostMalloc((void **)&E->hres, sizeof(double) * 4 * n, hipHostMallocDefault) != hipSuccess) {
+        E->hres = nullptr;
+        return SU2_ENOMEM;
+    }
+    E->hst.seed = seed;
+    E->hst.sweep = 0;
+    E->hst.run_base = 0;
+    HIPCHK(hipMemsetAsync(E->st, 0, sizeof(DevState), E->stream()));
+    CHK(upload_state(E));
+    CHK(build_tiles(E));
+    KArgs a = kargs(E);
+    su2::launch_init(a, E->f32, start == SU2_HOT ? 1 : 0, E->block, E->grid, E->stream());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    return SU2_OK;
+}
+
+void destroy_common(su2_ensemble_s *E) {
+    if (!E) return;
+    (void)hipSetDevice(E->device);
+    if (E->own) (void)hipStreamSynchronize(E->own);
+    if (E->user) (void)hipStreamSynchronize(E->user);
+    drop_graphs(E);
+    for (auto &p : E->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : E->evpool) (void)hipEventDestroy(e);
+    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->st, E->tries_part, E->part_plaq,
+                    E->part_poly, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1], E->wl_t,
+                    E->wl_s, E->wpart, E->trace};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (E->own_links && E->links) (void)hipFree(E->links);
+    if (E->hres) (void)hipHostFree(E->hres);
+    if (E->own) (void)hipStreamDestroy(E->own);
+}
+
+// ---- one sweep --------------------------------------------------------------
+su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
+    const KArgs a = kargs(E);
+    for (int mu = 0; mu < 4; ++mu)
+        for (int par = 0; par < 2; ++par) {
+            Timed t(E, SU2_K_HEATBATH, s);
+            su2::launch_heatbath(a, E->f32, mu, par, E->block, E->grid, s, E->trace != nullptr);
+            t.done(s);
+        }
+    if (meas & 1) {
+        Timed t(E, SU2_K_PLAQUETTE, s);
+        su2::launch_plaquette(a, E->f32, E->part_plaq, E->block, E->grid, s);
+        t.done(s);
+        Timed r(E, SU2_K_REDUCE, s);
+        su2::launch_finalize(E->ddesc, E->n, E->part_plaq, 0, E->st, 1, E->ser_plaq, E->ser_cap, s);
+        r.done(s);
+    }
+    if (meas & 2) {
+        const KArgs sa = kargs(E, 1);
+        Timed t(E, SU2_K_POLYAKOV, s);
+        su2::launch_polyakov(sa, E->f32, E->part_poly, E->block, E->grid, s);
+        t.done(s);
+        Timed r(E, SU2_K_REDUCE, s);
+        su2::launch_finalize(E->ddesc, E->n, E->part_poly, 1, E->st, 1, E->ser_poly, E->ser_cap, s);
+        r.done(s);
+    }
+    su2::launch_bump(E->st, s);
+    HIPCHK(hipGetLastError());
+    return SU2_OK;
+}
+
+su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas) {
+    hipStream_t s = E->stream();
+    const bool use_graph = !E->timing && nsweeps > 1 && !std::getenv("SU2_NO_GRAPH");
+    if (use_graph) {
+        if (!E->gexec[meas]) {
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
+            su2_status st = enqueue_sweep(E, meas, E->own);
+            hipGraph_t gg = nullptr;
+            hipError_t e = hipStreamEndCapture(E->own, &gg);
+            if (st != SU2_OK) return st;
+            HIPCHK(e);
+            g = gg;
+            HIPCHK(hipGraphInstantiate(&E->gexec[meas], g, nullptr, nullptr, 0));
+            HIPCHK(hipGraphDestroy(g));
+        }
+        for (int k = 0; k < nsweeps; ++k) HIPCHK(hipGraphLaunch(E->gexec[meas], s));
+    } else {
+        for (int k = 0; k < nsweeps; ++k) CHK(enqueue_sweep(E, meas, s));
+    }
+    E->hst.sweep += (unsigned)nsweeps;
+    E->updates += (unsigned long long)nsweeps * (unsigned long long)E->total_links;
+    invalidate_measure_buffers(E);
+    return SU2_OK;
+}
+
+su2_status ensure_series(su2_ensemble_s *E, int nsweeps) {
+    if (nsweeps <= E->ser_cap) return SU2_OK;
+    int cap = 64;
+    while (cap < nsweeps) cap *= 2;
+    CHK(dalloc(E, &E->ser_plaq, sizeof(double) * (size_t)cap * E->n));
+    CHK(dalloc(E, &E->ser_poly, sizeof(double) * (size_t)cap * E->n));
+    E->ser_cap = cap;
+    drop_graphs(E);
+    return SU2_OK;
+}
+
+su2_status set_seed(su2_ensemble_s *E, uint64_t seed) {
+    if (E->hst.seed != seed) {
+        E->hst.seed = seed;
+        CHK(upload_state(E));
+    }
+    return SU2_OK;
+}
+
+// ---- measurements -------------------------------------------------------------
+su2_status measure_plaquette(su2_ensemble_s *E, int l, double *avg, double *sp, double *tp) {
+    hipStream_t s = E->stream();
+    const KArgs a = kargs(E);
+    {
+        Timed t(E, SU2_K_PLAQUETTE, s);
+        su2::launch_plaquette(a, E->f32, E->part_plaq, E->block, E->grid, s);
+        t.done(s);
+    }
+    {
+        Timed t(E, SU2_K_REDUCE, s);
+        su2::launch_finalize(E->ddesc, E->n, E->part_plaq, 0, E->st, 0, E->res, 4, s);
+        t.done(s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(E->hres, E->res, sizeof(double) * 4 * E->n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (avg) *avg = E->hres[4 * l + 0];
+    if (sp) *sp = E->hres[4 * l + 1];
+    if (tp) *tp = E->hres[4 * l + 2];
+    return check_err(E);
+}
+
+su2_status measure_polyakov(su2_ensemble_s *E, int l, double *out) {
+    hipStream_t s = E->stream();
+    const KArgs a = kargs(E, 1);
+    {
+        Timed t(E, SU2_K_POLYAKOV, s);
+        su2::launch_polyakov(a, E->f32, E->part_poly, E->block, E->grid, s);
+        t.done(s);
+    }
+    {
+        Timed t(E, SU2_K_REDUCE, s);
+        su2::launch_finalize(E->ddesc, E->n, E->part_poly, 1, E->st, 0, E->res, 4, s);
+        t.done(s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(E->hres, E->res, sizeof(double) * 4 * E->n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (out) *out = E->hres[4 * l];
+    return check_err(E);
+}
+
+bool finite_unit(const double *u, double tol) {
+    double n2 = 0;
+    for (int c = 0; c < 4; ++c) {
+        if (!std::isfinite(u[c])) return false;
+        n2 += u[c] * u[c];
+    }
+    return std::fabs(1.0 - n2) <= tol;
+}
+
+// canonical host <-> device for lattice l
+su2_status set_links_l(su2_ensemble_s *E, int l, const double *host) {
+    const LatDesc &d = E->hdesc[l];
+    const long long V = 2LL * d.vh;
+    for (long long i = 0; i < 4 * V; ++i)
+        if (!finite_unit(host + 4 * i, 1e-6)) return SU2_EINVAL;
+    double *stage = nullptr;
+    CHK(dalloc(E, &stage, sizeof(double) * 16 * (size_t)E->total_sites));
+    hipStream_t s = E->stream();
+    HIPCHK(hipMemcpyAsync(stage + 4 * d.off, host, sizeof(double) * 16 * V, hipMemcpyHostToDevice, s));
+    // only the tiles of lattice l
+    KArgs a = kargs(E);
+    a.tiles = E->tiles + d.tile0;
+    a.ntiles = d.ntile;
+    su2::launch_from_canon(a, E->f32, stage, E->block, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(stage));
+    invalidate_measure_buffers(E);
+    return SU2_OK;
+}
+
+su2_status get_links_l(su2_ensemble_s *E, int l, const void *src, int ndir, double *host) {
+    const LatDesc &d = E->hdesc[l];
+    const long long V = 2LL * d.vh;
+    double *stage = nullptr;
+    CHK(dalloc(E, &stage, sizeof(double) * 4 * ndir * (size_t)E->total_sites));
+    hipStream_t s = E->stream();
+    KArgs a = kargs(E);
+    a.tiles = E->tiles + d.tile0;
+    a.ntiles = d.ntile;
+    su2::launch_to_canon(a, E->f32, src, ndir, stage, E->block, s);
+    HIPCHK(hipGetLastError());
+    const long long base = ndir == 4 ? d.off : d.soff;
+    HIPCHK(hipMemcpyAsync(host, stage + 4 * base, sizeof(double) * 4 * ndir * V, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(stage));
+    return SU2_OK;
+}
+
+su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, double *defect) {
+    if (tries) {
+        std::vector<unsigned long long> h(E->ntiles);
+        HIPCHK(hipMemcpyAsync(h.data(), E->tries_part, sizeof(unsigned long long) * E->ntiles,
+                              hipMemcpyDeviceToHost, E->stream()));
+        HIPCHK(hipStreamSynchronize(E->stream()));
+        unsigned long long t = E->tries_acc;
+        for (auto v : h) t += v;
+        *tries = t;
+    }
+    if (updates) *updates = E->updates;
+    if (defect) {
+        unsigned long long *m = nullptr;
+        CHK(dalloc(E, &m, sizeof(unsigned long long)));
+        HIPCHK(hipMemsetAsync(m, 0, sizeof(unsigned long long), E->stream()));
+        su2::launch_unit_defect(kargs(E), E->f32, m, E->block, E->stream());
+        HIPCHK(hipGetLastError());
+        unsigned long long bits = 0;
+        HIPCHK(hipMemcpyAsync(&bits, m, sizeof(bits), hipMemcpyDeviceToHost, E->stream()));
+        HIPCHK(hipStreamSynchronize(E->stream()));
+        HIPCHK(hipFree(m));
+        std::memcpy(defect, &bits, sizeof(double));
+    }
+    return check_err(E);
+}
+
+su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap) {
+    if (block < 64 || block > 256 || (block & 63)) return SU2_EINVAL;
+    if (grid < 0 || (grid & 7)) return SU2_EINVAL;
+    if (remap != 0 && remap != 1) return SU2_EINVAL;
+    const bool reshape = block != E->block;
+    E->grid = grid;
+    E->remap = remap;
+    if (reshape) {
+        E->block = block;
+        CHK(build_tiles(E));
+    }
+    drop_graphs(E);
+    return SU2_OK;
+}
+
+// Time one sweep per candidate shape; links, sweep counter and tries are
+// restored afterwards.
+std::map<std::string, int3> g_tune_cache;
+
+su2_status autotune_common(su2_ensemble_s *E) {
+    char key[160];
+    std::snprintf(key, sizeof key, "%s:n%d:sites%lld:t%lld", E->f32 ? "f32" : "f64", E->n, E->total_sites,
+                  (long long)E->hdesc[0].n[3]);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return set_launch_common(E, it->second.x, it->second.y, it->second.z);
+
+    hipStream_t s = E->stream();
+    void *backup = nullptr;
+    CHK(dalloc(E, &backup, E->link_bytes));
+    HIPCHK(hipMemcpyAsync(backup, E->links, E->link_bytes, hipMemcpyDeviceToDevice, s));
+    CHK(fold_tries(E));
+    const unsigned long long tries0 = E->tries_acc, upd0 = E->updates;
+    const DevState st0 = E->hst;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, E->device));
+    const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const bool timing0 = E->timing;
+    E->timing = false;
+
+    const int blocks[] = {64, 128, 256};
+    const int gmul[] = {0, 4, 8, 16};
+    hipEvent_t ea, eb;
+    HIPCHK(hipEventCreate(&ea));
+    HIPCHK(hipEventCreate(&eb));
+    float best = 1e30f;
+    int3 bestc = make_int3(E->block, E->grid, E->remap);
+    for (int b : blocks)
+        for (int gm : gmul)
+            for (int rm = 0; rm < 2; ++rm) {
+                const int g = gm ? gm * cus / 8 * 8 : 0;
+                CHK(set_launch_common(E, b, g, rm));
+                CHK(enqueue_sweep(E, 0, s));  // warm-up
+                HIPCHK(hipEventRecord(ea, s));
+                for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 0, s));
+                HIPCHK(hipEventRecord(eb, s));
+                HIPCHK(hipEventSynchronize(eb));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ea, eb));
+                if (ms < best) {
+                    best = ms;
+                    bestc = make_int3(b, g, rm);
+                }
+            }
+    HIPCHK(hipEventDestroy(ea));
+    HIPCHK(hipEventDestroy(eb));
+    CHK(set_launch_common(E, bestc.x, bestc.y, bestc.z));
+    HIPCHK(hipMemcpyAsync(E->links, backup, E->link_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(backup));
+    E->tries_acc = tries0;
+    E->updates = upd0;
+    E->hst = st0;
+    CHK(upload_state(E));
+    E->timing = timing0;
+    g_tune_cache[key] = bestc;
+    invalidate_measure_buffers(E);
+    return SU2_OK;
+}
+
+su2_status get_timing_common(su2_ensemble_s *E, su2_kernel_kind kind, double *ms, int64_t *launches) {
+    if ((int)kind < 0 || kind >= SU2_K_COUNT) return SU2_EINVAL;
+    CHK(collect_timing(E));
+    if (ms) *ms = E->tms[kind];
+    if (launches) *launches = E->tcount[kind];
+    return SU2_OK;
+}
+
+su2_status set_timing_common(su2_ensemble_s *E, int enable) {
+    CHK(collect_timing(E));
+    E->timing = enable != 0;
+    for (int k = 0; k < SU2_K_COUNT; ++k) {
+        E->tms[k] = 0;
+        E->tcount[k] = 0;
+    }
+    return SU2_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char *su2_status_str(su2_status st) {
+    switch (st) {
+    case SU2_OK: return "ok";
+    case SU2_EINVAL: return "invalid argument";
+    case SU2_ENOMEM: return "out of memory";
+    case SU2_ENODEV: return "no GPU device";
+    case SU2_EDEVICE: return "GPU runtime error";
+    case SU2_ESTATE: return "handle failed or call out of sequence";
+    case SU2_EIO: return "I/O error";
+    case SU2_ENUMERIC: return "non-finite value or sampler failure";
+    }
+    return "unknown status";
+}
+
+size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec) {
+    const int d[4] = {Nx, Ny, Nz, Nt};
+    if (!dims_ok(d) || (prec != SU2_F32 && prec != SU2_F64)) return 0;
+    return (size_t)4 * Nx * Ny * Nz * (size_t)Nt * link_size(prec == SU2_F32);
+}
+
+// ---- ensembles -------------------------------------------------------------
+su2_status su2_ensemble_create(int n, const int *dims, const double *betas, su2_start start, uint64_t seed,
+                               su2_prec prec, void *device_links, size_t device_bytes, su2_ensemble *out) {
+    if (!out || n <= 0 || !dims || !betas) return SU2_EINVAL;
+    *out = nullptr;
+    if ((start != SU2_COLD && start != SU2_HOT) || (prec != SU2_F32 && prec != SU2_F64)) return SU2_EINVAL;
+    if (n > (1 << 23)) return SU2_EINVAL;
+    long long sites = 0;
+    for (int l = 0; l < n; ++l) {
+        if (!dims_ok(dims + 4 * l)) return SU2_EINVAL;
+        if (!(betas[l] >= 0.0) || !std::isfinite(betas[l])) return SU2_EINVAL;
+        sites += (long long)dims[4 * l] * dims[4 * l + 1] * dims[4 * l + 2] * dims[4 * l + 3];
+    }
+    if (sites > (1LL << 31)) return SU2_EINVAL;
+    auto *E = new (std::nothrow) su2_ensemble_s();
+    if (!E) return SU2_ENOMEM;
+    su2_status st = create_common(n, dims, betas, start, seed, prec, device_links, device_bytes, E);
+    if (st != SU2_OK) {
+        destroy_common(E);
+        delete E;
+        return st;
+    }
+    *out = E;
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_destroy(su2_ensemble ens) {
+    if (!ens) return SU2_EINVAL;
+    destroy_common(ens);
+    delete ens;
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_set_stream(su2_ensemble E, void *stream) {
+    CHK(enter(E));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    E->user = (hipStream_t)stream;
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_set_sampler(su2_ensemble E, su2_sampler sampler) {
+    CHK(enter(E));
+    if (sampler != SU2_HYBRID && sampler != SU2_CREUTZ) return SU2_EINVAL;
+    if (E->sampler != (int)sampler) drop_graphs(E);
+    E->sampler = (int)sampler;
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, uint64_t seed, double *plaq, double *poly) {
+    CHK(enter(E));
+    if (nsweeps < 0) return SU2_EINVAL;
+    if (nsweeps == 0) return SU2_OK;
+    const int meas = (plaq ? 1 : 0) | (poly ? 2 : 0);
+    if (meas) CHK(ensure_series(E, nsweeps));
+    E->hst.seed = seed;
+    E->hst.run_base = E->hst.sweep;
+    CHK(upload_state(E));
+    CHK(run_sweeps(E, nsweeps, meas));
+    if (meas) {
+        std::vector<double> h((size_t)E->ser_cap * E->n);
+        hipStream_t s = E->stream();
+        for (int m = 0; m < 2; ++m) {
+            double *dst = m == 0 ? plaq : poly;
+            if (!dst) continue;
+            HIPCHK(hipMemcpyAsync(h.data(), m == 0 ? E->ser_plaq : E->ser_poly, sizeof(double) * h.size(),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int l = 0; l < E->n; ++l)
+                for (int k = 0; k < nsweeps; ++k) dst[(size_t)l * nsweeps + k] = h[(size_t)l * E->ser_cap + k];
+        }
+        return check_err(E);
+    }
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_get_links(su2_ensemble E, int i, double *host) {
+    CHK(enter(E));
+    if (i < 0 || i >= E->n || !host) return SU2_EINVAL;
+    return get_links_l(E, i, E->links, 4, host);
+}
+
+su2_status su2_ensemble_set_links(su2_ensemble E, int i, const double *host) {
+    CHK(enter(E));
+    if (i < 0 || i >= E->n || !host) return SU2_EINVAL;
+    return set_links_l(E, i, host);
+}
+
+su2_status su2_ensemble_stats(su2_ensemble E, uint64_t *tries, uint64_t *updates) {
+    CHK(enter(E));
+    return stats_common(E, tries, updates, nullptr);
+}
+
+su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap) {
+    CHK(enter(E));
+    return set_launch_common(E, block, grid, xcd_remap);
+}
+
+su2_status su2_ensemble_autotune(su2_ensemble E) {
+    CHK(enter(E));
+    return autotune_common(E);
+}
+
+su2_status su2_ensemble_set_timing(su2_ensemble E, int enable) {
+    CHK(enter(E));
+    return set_timing_common(E, enable);
+}
+
+su2_status su2_ensemble_get_timing(su2_ensemble E, su2_kernel_kind kind, double *ms, int64_t *launches) {
+    CHK(enter(E));
+    return get_timing_common(E, kind, ms, launches);
+}
+
+// ---- single lattice ----------------------------------------------------------
+su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t seed, su2_prec prec,
+                      void *device_links, size_t device_bytes, su2_lattice *out) {
+    if (!out) return SU2_EINVAL;
+    *out = nullptr;
+    const int d[4] = {Nx, Ny, Nz, Nt};
+    if (!dims_ok(d)) return SU2_EINVAL;
+    if ((start != SU2_COLD && start != SU2_HOT) || (prec != SU2_F32 && prec != SU2_F64)) return SU2_EINVAL;
+    auto *E = new (std::nothrow) su2_lattice_s();
+    if (!E) return SU2_ENOMEM;
+    const double beta = 0.0;
+    su2_status st = create_common(1, d, &beta, start, seed, prec, device_links, device_bytes, E);
+    if (st != SU2_OK) {
+        destroy_common(E);
+        delete E;
+        return st;
+    }
+    *out = E;
+    return SU2_OK;
+}
+
+su2_status su2_destroy(su2_lattice E) {
+    if (!E) return SU2_EINVAL;
+    destroy_common(E);
+    delete E;
+    return SU2_OK;
+}
+
+su2_status su2_set_stream(su2_lattice E, void *stream) { return su2_ensemble_set_stream(E, stream); }
+su2_status su2_set_sampler(su2_lattice E, su2_sampler s) { return su2_ensemble_set_sampler(E, s); }
+
+static su2_status set_beta(su2_ensemble_s *E, double beta) {
+    if (E->hdesc[0].beta != beta) {
+        E->hdesc[0].beta = beta;
+        E->hdesc[0].betaf = (float)beta;
+        CHK(upload_desc(E));
+    }
+    return SU2_OK;
+}
+
+su2_status su2_heatbath(su2_lattice E, double beta, int nsweeps, uint64_t seed) {
+    CHK(enter(E));
+    if (!(beta >= 0.0) || !std::isfinite(beta) || nsweeps < 0) return SU2_EINVAL;
+    if (nsweeps == 0) return SU2_OK;
+    CHK(set_beta(E, beta));
+    CHK(set_seed(E, seed));
+    return run_sweeps(E, nsweeps, 0);
+}
+
+su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int mu, int parity) {
+    CHK(enter(E));
+    if (!(beta >= 0.0) || !std::isfinite(beta) || mu < 0 || mu > 3 || (parity != 0 && parity != 1))
+        return SU2_EINVAL;
+    CHK(set_beta(E, beta));
+    CHK(set_seed(E, seed));
+    hipStream_t s = E->stream();
+    {
+        Timed t(E, SU2_K_HEATBATH, s);
+        su2::launch_heatbath(kargs(E), E->f32, mu, parity, E->block, E->grid, s, E->trace != nullptr);
+        t.done(s);
+    }
+    HIPCHK(hipGetLastError());
+    E->updates += (unsigned long long)E->total_links / 8;
+    invalidate_measure_buffers(E);
+    return SU2_OK;
+}
+
+su2_status su2_overrelax(su2_lattice E, int nsweeps) {
+    CHK(enter(E));
+    if (nsweeps < 0) return SU2_EINVAL;
+    hipStream_t s = E->stream();
+    const KArgs a = kargs(E);
+    for (int k = 0; k < nsweeps; ++k)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par) {
+                Timed t(E, SU2_K_OVERRELAX, s);
+                su2::launch_overrelax(a, E->f32, mu, par, E->block, E->grid, s);
+                t.done(s);
+            }
+    HIPCHK(hipGetLastError());
+    if (nsweeps) invalidate_measure_buffers(E);
+    return SU2_OK;
+}
+
+su2_status su2_plaquette(su2_lattice E, double *avg, double *sp, double *tp) {
+    CHK(enter(E));
+    return measure_plaquette(E, 0, avg, sp, tp);
+}
+
+su2_status su2_polyakov(su2_lattice E, double *avg) {
+    CHK(enter(E));
+    return measure_polyakov(E, 0, avg);
+}
+
+su2_status su2_ape_smear(su2_lattice E, double alpha, int nsteps) {
+    CHK(enter(E));
+    if (!(alpha >= 0.0 && alpha <= 1.0) || nsteps < 0) return SU2_EINVAL;
+    const size_t bytes = (size_t)3 * E->total_sites * link_size(E->f32);
+    for (int b = 0; b < 2; ++b)
+        if (!E->sm[b]) CHK(dalloc(E, &E->sm[b], bytes));
+    hipStream_t s = E->stream();
+    const KArgs a = kargs(E);
+    const void *src = E->links;
+    int raw = 1, cur = 0;
+    if (nsteps == 0) {  // smeared copy = raw spatial links
+        su2::launch_ape(a, E->f32, E->links, 1, E->sm[0], 0.0, E->block, E->grid, s);
+        cur = 0;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        cur = k & 1;
+        Timed t(E, SU2_K_APE, s);
+        su2::launch_ape(a, E->f32, src, raw, E->sm[cur], alpha, E->block, E->grid, s);
+        t.done(s);
+        src = E->sm[cur];
+        raw = 0;
+    }
+    HIPCHK(hipGetLastError());
+    E->sm_cur = cur;
+    return SU2_OK;
+}
+
+su2_status su2_get_smeared(su2_lattice E, double *host) {
+    CHK(enter(E));
+    if (!host) return SU2_EINVAL;
+    if (E->sm_cur < 0) return SU2_ESTATE;
+    return get_links_l(E, 0, E->sm[E->sm_cur], 3, host);
+}
+
+su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
+    CHK(enter(E));
+    const LatDesc &d = E->hdesc[0];
+    const int smin = std::min(d.n[0], std::min(d.n[1], d.n[2]));
+    if (!out || Rmax < 1 || Tmax < 1 || Rmax > smin || Tmax > d.n[3] || Tmax > 32) return SU2_EINVAL;
+    const size_t qb = link_size(E->f32);
+    const long long V = E->total_sites;
+    const size_t tb = qb * (size_t)Tmax * V, sb = qb * (size_t)3 * Rmax * V;
+    if (tb > E->wl_t_bytes) {
+        CHK(dalloc(E, &E->wl_t, tb));
+        E->wl_t_bytes = tb;
+    }
+    if (sb > E->wl_s_bytes) {
+        CHK(dalloc(E, &E->wl_s, sb));
+        E->wl_s_bytes = sb;
+    }
+    const size_t pb = sizeof(double) * 2 * (size_t)Rmax * E->nvtiles * Tmax;
+    if (pb > E->wpart_bytes) {
+        CHK(dalloc(E, &E->wpart, pb));
+        E->wpart_bytes = pb;
+    }
+    hipStream_t s = E->stream();
+    const KArgs va = kargs(E, 2);
+    const bool sm = E->sm_cur >= 0;
+    Timed t(E, SU2_K_WILSON, s);
+    su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, Tmax, E->wl_t, E->wl_s,
+                       E->block, s);
+    su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_t, E->wl_s, E->wpart, s);
+    double *dout = nullptr;
+    CHK(dalloc(E, &dout, sizeof(double) * Rmax * Tmax));
+    su2::launch_wfinal(E->ddesc, E->nvtiles, Rmax, Tmax, E->wpart, dout, s);
+    t.done(s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, dout, sizeof(double) * Rmax * Tmax, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(dout));
+    return check_err(E);
+}
+
+su2_status su2_get_links(su2_lattice E, double *host) {
+    CHK(enter(E));
+    if (!host) return SU2_EINVAL;
+    return get_links_l(E, 0, E->links, 4, host);
+}
+
+su2_status su2_set_links(su2_lattice E, const double *host) {
+    CHK(enter(E));
+    if (!host) return SU2_EINVAL;
+    return set_links_l(E, 0, host);
+}
+
+su2_status su2_device_links(su2_lattice E, void **ptr, size_t *bytes) {
+    CHK(enter(E));
+    if (ptr) *ptr = E->links;
+    if (bytes) *bytes = E->link_bytes;
+    return SU2_OK;
+}
+
+su2_status su2_get_sweep(su2_lattice E, uint32_t *sweep) {
+    CHK(enter(E));
+    if (!sweep) return SU2_EINVAL;
+    *sweep = E->hst.sweep;
+    return SU2_OK;
+}
+
+su2_status su2_set_sweep(su2_lattice E, uint32_t sweep) {
+    CHK(enter(E));
+    E->hst.sweep = sweep;
+    return upload_state(E);
+}
+
+su2_status su2_stats(su2_lattice E, uint64_t *tries, uint64_t *updates, double *defect) {
+    CHK(enter(E));
+    return stats_common(E, tries, updates, defect);
+}
+
+su2_status su2_trace_tries(su2_lattice E, int enable) {
+    CHK(enter(E));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    if (enable) {
+        if (!E->trace) {
+            CHK(dalloc(E, &E->trace, sizeof(uint32_t) * 4 * (size_t)E->total_sites));
+            HIPCHK(hipMemsetAsync(E->trace, 0, sizeof(uint32_t) * 4 * (size_t)E->total_sites, E->stream()));
+        }
+    } else if (E->trace) {
+        HIPCHK(hipFree(E->trace));
+        E->trace = nullptr;
+    }
+    drop_graphs(E);
+    return SU2_OK;
+}
+
+su2_status su2_get_tries(su2_lattice E, uint32_t *host) {
+    CHK(enter(E));
+    if (!host) return SU2_EINVAL;
+    if (!E->trace) return SU2_ESTATE;
+    HIPCHK(hipMemcpyAsync(host, E->trace, sizeof(uint32_t) * 4 * (size_t)E->total_sites, hipMemcpyDeviceToHost,
+                          E->stream()));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    return SU2_OK;
+}
+
+// checkpoint format: "SU2CKPT1", u32 version, i32 Nx Ny Nz Nt, i32 prec,
+// u32 sweep, u64 seed, then 16 V float64 in the canonical layout
+su2_status su2_save(su2_lattice E, const char *path) {
+    CHK(enter(E));
+    if (!path) return SU2_EINVAL;
+    const LatDesc &d = E->hdesc[0];
+    const long long V = 2LL * d.vh;
+    std::vector<double> h((size_t)16 * V);
+    CHK(get_links_l(E, 0, E->links, 4, h.data()));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return SU2_EIO;
+    const char magic[8] = {'S', 'U', '2', 'C', 'K', 'P', 'T', '1'};
+    const uint32_t version = 1;
+    const int32_t hdr[5] = {d.n[0], d.n[1], d.n[2], d.n[3], E->f32 ? (int32_t)SU2_F32 : (int32_t)SU2_F64};
+    const uint32_t sweep = E->hst.sweep;
+    const uint64_t seed = E->hst.seed;
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&version, 4, 1, f) == 1 &&
+              std::fwrite(hdr, 4, 5, f) == 5 && std::fwrite(&sweep, 4, 1, f) == 1 &&
+              std::fwrite(&seed, 8, 1, f) == 1 && std::fwrite(h.data(), 8, h.size(), f) == h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? SU2_OK : SU2_EIO;
+}
+
+su2_status su2_load(const char *path, su2_lattice *out) {
+    if (!path || !out) return SU2_EINVAL;
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return SU2_EIO;
+    char magic[8];
+    uint32_t version = 0, sweep = 0;
+    int32_t hdr[5];
+    uint64_t seed = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "SU2CKPT1", 8) == 0 &&
+              std::fread(&version, 4, 1, f) == 1 && version == 1 && std::fread(hdr, 4, 5, f) == 5 &&
+              std::fread(&sweep, 4, 1, f) == 1 && std::fread(&seed, 8, 1, f) == 1;
+    if (!ok || !dims_ok(hdr) || (hdr[4] != SU2_F32 && hdr[4] != SU2_F64)) {
+        std::fclose(f);
+        return SU2_EIO;
+    }
+    const long long V = (long long)hdr[0] * hdr[1] * hdr[2] * hdr[3];
+    std::vector<double> h((size_t)16 * V);
+    ok = std::fread(h.data(), 8, h.size(), f) == h.size();
+    std::fclose(f);
+    if (!ok) return SU2_EIO;
+    su2_lattice E = nullptr;
+    CHK(su2_create(hdr[0], hdr[1], hdr[2], hdr[3], SU2_COLD, seed, (su2_prec)hdr[4], nullptr, 0, &E));
+    su2_status st = set_links_l(E, 0, h.data());
+    if (st == SU2_OK) {
+        E->hst.sweep = sweep;
+        E->hst.seed = seed;
+        st = upload_state(E);
+    }
+    if (st != SU2_OK) {
+        su2_destroy(E);
+        return st == SU2_EINVAL ? SU2_EIO : st;
+    }
+    *out = E;
+    return SU2_OK;
+}
+
+su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap) {
+    return su2_ensemble_set_launch(E, block, grid, remap);
+}
+
+su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap) {
+    CHK(enter(E));
+    if (block) *block = E->block;
+    if (grid) *grid = E->grid;
+    if (remap) *remap = E->remap;
+    return SU2_OK;
+}
+
+su2_status su2_autotune(su2_lattice E, double beta) {
+    CHK(enter(E));
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return SU2_EINVAL;
+    CHK(set_beta(E, beta));
+    return autotune_common(E);
+}
+
+su2_status su2_set_timing(su2_lattice E, int enable) { return su2_ensemble_set_timing(E, enable); }
+
+su2_status su2_get_timing(su2_lattice E, su2_kernel_kind kind, double *ms, int64_t *launches) {
+    return su2_ensemble_get_timing(E, kind, ms, launches);
+}
+
+}  // extern "C"

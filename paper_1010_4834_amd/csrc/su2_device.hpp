@@ -1,0 +1,269 @@
+// su2_device.hpp -- device-side building blocks of the gfx950 SU(2) library:
+// lattice descriptors, SU(2) quaternion algebra, the Philox4x32-10 stream,
+// per-precision math and compensated binary64 reductions.
+//
+// Method: Cardoso & Bicudo, "SU(2) Lattice Gauge Theory Simulations on Fermi
+// GPUs" (arXiv:1010.4834).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace su2 {
+
+// ---------------------------------------------------------------------------
+// Lattice descriptor, one per lattice of a batch (read with scalar loads).
+// Link storage of lattice l: links [off, off + 4V) ordered [mu][parity][cb],
+// cb = s >> 1 with s = x + Nx*(y + Ny*(z + Nz*t)) (Nx even, so the sites of
+// one parity in an x-row are contiguous).  A float link is one float4; a
+// double link lives in two float64x2 planes: within the (mu, parity) block
+// starting at link b, components (a0,a1) at double2 index 2b + cb and
+// (a2,a3) at 2b + vh + cb.  Every wavefront load is one contiguous 1 KiB.
+struct LatDesc {
+    int n[4];        // extents Nx, Ny, Nz, Nt (even, >= 2)
+    int hx;          // Nx / 2
+    int vh;          // V / 2
+    int ns;          // Nx * Ny * Nz
+    int lat_id;      // lattice id in the Philox counter
+    long long off;   // first link of this lattice in the link buffer
+    long long soff;  // first link in the smeared-link buffers (3V links)
+    long long toff;  // first entry of the per-link try record ([s][mu])
+    double inv_hx, inv_ny, inv_nz, inv_nx;  // 1/d for the division helper
+    double beta;
+    float betaf;
+    int tile0, ntile;    // range in the half-site tile table
+    int stile0, nstile;  // range in the spatial-site tile table
+    int vtile0, nvtile;  // range in the full-site tile table
+};
+
+// Mutable state read by the kernels; lives in device memory so that one
+// captured graph serves every sweep.
+struct DevState {
+    unsigned long long seed;
+    unsigned int sweep;     // Philox sweep word of the sweep in progress
+    unsigned int run_base;  // sweep index of the first sweep of a series
+    unsigned int err;       // sampler try-cap hits (non-finite input)
+    unsigned int pad;
+};
+
+// A tile: lattice index and first index (half-site, spatial site or site).
+typedef int2 Tile;
+
+// Random-number purposes (third Philox counter word).
+constexpr uint32_t PURPOSE_HEATBATH = 0;
+constexpr uint32_t PURPOSE_HOT = 1;
+constexpr uint32_t MAX_TRIES = 4096;  // never reached for finite links
+
+__device__ __forceinline__ uint32_t tag(int lat_id, uint32_t purpose, int mu, int parity) {
+    return ((uint32_t)lat_id << 8) | (purpose << 4) | ((uint32_t)mu << 1) | (uint32_t)parity;
+}
+
+// q = n / d, r = n % d for 0 <= n < 2^31 with a binary64 reciprocal and a
+// one-step correction (the product is within one of the true quotient).
+__device__ __forceinline__ void udiv(int n, int d, double inv, int &q, int &r) {
+    int qq = (int)((double)n * inv);
+    int rr = n - qq * d;
+    if (rr < 0) { --qq; rr += d; }
+    else if (rr >= d) { ++qq; rr -= d; }
+    q = qq;
+    r = rr;
+}
+
+// ---------------------------------------------------------------------------
+// SU(2) as four reals, U = a0 + i a.sigma (paper Sec. 2).
+template <class T> struct Q { T a, b, c, d; };
+
+template <class T>
+__device__ __forceinline__ Q<T> qmul(const Q<T> &x, const Q<T> &y) {
+    // (x0 y0 - x.y,  x0 y + y0 x - x cross y)
+    Q<T> r;
+    r.a = x.a * y.a - x.b * y.b - x.c * y.c - x.d * y.d;
+    r.b = x.a * y.b + y.a * x.b - (x.c * y.d - x.d * y.c);
+    r.c = x.a * y.c + y.a * x.c - (x.d * y.b - x.b * y.d);
+    r.d = x.a * y.d + y.a * x.d - (x.b * y.c - x.c * y.b);
+    return r;
+}
+template <class T> __device__ __forceinline__ Q<T> qdag(const Q<T> &x) {
+    return Q<T>{x.a, -x.b, -x.c, -x.d};
+}
+template <class T> __device__ __forceinline__ void qacc(Q<T> &s, const Q<T> &x) {
+    s.a += x.a; s.b += x.b; s.c += x.c; s.d += x.d;
+}
+// 1/2 Re Tr(x y^dag) = x0 y0 + x.y
+template <class T> __device__ __forceinline__ T half_tr_xyd(const Q<T> &x, const Q<T> &y) {
+    return x.a * y.a + x.b * y.b + x.c * y.c + x.d * y.d;
+}
+template <class T> __device__ __forceinline__ Q<T> qone() { return Q<T>{T(1), T(0), T(0), T(0)}; }
+
+// Scale to unit norm with the squared norm and its reciprocal square root
+// evaluated in binary64 (the reunitarisation that keeps binary32 links on
+// the group).
+template <class T> __device__ __forceinline__ Q<T> qnormalize(const Q<T> &x) {
+    double a = x.a, b = x.b, c = x.c, d = x.d;
+    double n2 = a * a + b * b + c * c + d * d;
+    double inv = 1.0 / sqrt(n2);
+    return Q<T>{(T)(a * inv), (T)(b * inv), (T)(c * inv), (T)(d * inv)};
+}
+
+// ---------------------------------------------------------------------------
+// Link access.  `blk` is the first link of a (lattice, mu, parity) block.
+template <class T> struct Links;
+
+template <> struct Links<float> {
+    static __device__ __forceinline__ Q<float> ld(const void *base, long long blk, int vh, int cb) {
+        (void)vh;
+        float4 v = reinterpret_cast<const float4 *>(base)[blk + cb];
+        return Q<float>{v.x, v.y, v.z, v.w};
+    }
+    static __device__ __forceinline__ void st(void *base, long long blk, int vh, int cb,
+                                              const Q<float> &q) {
+        (void)vh;
+        reinterpret_cast<float4 *>(base)[blk + cb] = make_float4(q.a, q.b, q.c, q.d);
+    }
+};
+
+template <> struct Links<double> {
+    static __device__ __forceinline__ Q<double> ld(const void *base, long long blk, int vh, int cb) {
+        const double2 *p = reinterpret_cast<const double2 *>(base) + 2 * blk;
+        double2 lo = p[cb], hi = p[vh + cb];
+        return Q<double>{lo.x, lo.y, hi.x, hi.y};
+    }
+    static __device__ __forceinline__ void st(void *base, long long blk, int vh, int cb,
+                                              const Q<double> &q) {
+        double2 *p = reinterpret_cast<double2 *>(base) + 2 * blk;
+        p[cb] = make_double2(q.a, q.b);
+        p[vh + cb] = make_double2(q.c, q.d);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products on counter words 0 and 2 with a Weyl-advanced key.
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// Per-precision math.  binary32 uses the hardware transcendental units
+// (v_log_f32 is log2, v_sin/v_cos take revolutions); binary64 uses the
+// correctly rounded library routines.
+template <class T> struct Mth;
+
+template <> struct Mth<float> {
+    // (2m+1) 2^-24, m = the top 23 bits: exact, in (0,1)
+    static __device__ __forceinline__ float u(uint32_t w) {
+        return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f;
+    }
+    static __device__ __forceinline__ float ln(float x) {
+        return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+    }
+    static __device__ __forceinline__ float cos2pi(float r) { return __builtin_amdgcn_cosf(r); }
+    static __device__ __forceinline__ float sin2pi(float r) { return __builtin_amdgcn_sinf(r); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
+    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+    static __device__ __forceinline__ float nan_() { return __builtin_nanf(""); }
+};
+
+template <> struct Mth<double> {
+    static __device__ __forceinline__ double u(uint32_t w) {
+        return ((double)w * 2.0 + 1.0) * 0x1p-33;
+    }
+    static __device__ __forceinline__ double ln(double x) { return log(x); }
+    static __device__ __forceinline__ double cos2pi(double r) {
+        return cos(6.283185307179586476925286766559 * r);
+    }
+    static __device__ __forceinline__ double sin2pi(double r) {
+        return sin(6.283185307179586476925286766559 * r);
+    }
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+    static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+    static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+    static __device__ __forceinline__ double nan_() { return __builtin_nan(""); }
+};
+
+// ---------------------------------------------------------------------------
+// Compensated binary64 sums: (hi, lo) pairs combined with two-sum, in a
+// fixed order so that results are reproducible run to run.
+struct DD { double hi, lo; };
+
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+    double s = a.hi + b.hi;
+    double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b.hi - bb);
+    e += a.lo + b.lo;
+    double h = s + e;
+    return DD{h, e - (h - s)};
+}
+
+__device__ __forceinline__ DD dd_wave_sum(DD v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        DD o{__shfl_xor(v.hi, m, 64), __shfl_xor(v.lo, m, 64)};
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+// Block-wide sum of K pairs per thread; thread 0 receives the totals.
+// `lds` holds K * (blockDim.x / 64) pairs.  Every thread must call it.
+template <int K>
+__device__ __forceinline__ void dd_block_sum(DD (&v)[K], DD *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = dd_wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            DD t = lds[k];
+            for (int w = 1; w < nw; ++w) t = dd_add(t, lds[w * K + k]);
+            v[k] = t;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Tile walk of a persistent grid.  With xcd_remap, workgroup b runs on XCD
+// b % 8 (round-robin dispatch) and is given tiles from that XCD's
+// contiguous eighth of the tile list, so neighbouring tiles (which share
+// staple links) meet in the same L2.
+template <class F>
+__device__ __forceinline__ void for_each_tile(int ntiles, int xcd_remap, F &&body) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (xcd_remap && (G & 7) == 0) {
+        const int x = b & 7, j = b >> 3, gx = G >> 3;
+        const int tx = (ntiles + 7) >> 3;
+        for (int i = j; i < tx; i += gx) {
+            const int t = x * tx + i;
+            if (t >= ntiles) break;
+            body(t);
+        }
+    } else {
+        for (int t = b; t < ntiles; t += G) body(t);
+    }
+}
+
+}  // namespace su2

@@ -1,0 +1,44 @@
+// su2_internal.hpp -- kernel argument block and launcher declarations shared
+// by the kernels (su2_kernels.hip) and the C-ABI host code (su2_api.hip).
+#pragma once
+
+#include "su2_device.hpp"
+
+namespace su2 {
+
+// Arguments common to the lattice kernels (passed by value).
+struct KArgs {
+    const LatDesc *desc;                 // per-lattice descriptors
+    const Tile *tiles;                   // (lattice, first index) work list
+    int ntiles;
+    int xcd_remap;
+    void *links;                         // native link buffer
+    DevState *st;                        // seed / sweep counter / error flag
+    uint32_t *trace;                     // per-link try record or null
+    unsigned long long *tries_part;      // per-tile try counts
+    int sampler;                         // 0 hybrid, 1 Creutz
+};
+
+void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s,
+                     bool trace);
+void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s);
+void launch_init(const KArgs &a, bool f32, int hot, int block, int grid, hipStream_t s);
+void launch_from_canon(const KArgs &a, bool f32, const double *canon, int block, hipStream_t s);
+void launch_to_canon(const KArgs &a, bool f32, const void *src, int ndir, double *canon, int block,
+                     hipStream_t s);
+void launch_unit_defect(const KArgs &a, bool f32, unsigned long long *out, int block, hipStream_t s);
+void launch_plaquette(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
+void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
+void launch_finalize(const LatDesc *desc, int nlat, const double *part, int kind, const DevState *st,
+                     int series, double *out, long long ostride, hipStream_t s);
+void launch_bump(DevState *st, hipStream_t s);
+void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
+                int grid, hipStream_t s);
+void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,
+                   void *sl, int block, hipStream_t s);
+void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
+                   hipStream_t s);
+void launch_wfinal(const LatDesc *desc, int ntiles, int Rmax, int Tmax, const double *part, double *out,
+                   hipStream_t s);
+
+}  // namespace su2

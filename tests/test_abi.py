@@ -1,0 +1,53 @@
+"""Host-side checks of the C ABI (no GPU needed): every entry point declared
+in include/su2.h is exported by libsu2.so and bound in Python; argument
+validation and the no-device path."""
+import os
+import re
+import subprocess
+
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "su2.h")).read()
+    return set(re.findall(r"^(?:su2_status|size_t|const char \*)\s*(su2_\w+)\(", text, re.M))
+
+
+def test_header_symbols_exported():
+    from paper_1010_4834_amd import su2
+    names = declared()
+    assert len(names) >= 40
+    out = subprocess.run(["nm", "-D", "--defined-only", su2.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (su2_\w+)$", out, re.M))
+    assert names <= exported, names - exported
+    assert names == set(su2.EXPORTED), names ^ set(su2.EXPORTED)
+
+
+def test_host_validation():
+    from paper_1010_4834_amd import su2
+    assert su2.su2_link_bytes(8, 8, 8, 8, su2.F32) == 4 * 8**4 * 16
+    assert su2.su2_link_bytes(8, 8, 8, 8, su2.F64) == 4 * 8**4 * 32
+    for bad in ((7, 8, 8, 8), (8, 8, 8, 0), (8, 1, 8, 8)):
+        assert su2.su2_link_bytes(*bad, su2.F32) == 0
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_create(*bad, su2.COLD, 1, su2.F32)
+        assert e.value.status == su2.EINVAL
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_create(8, 8, 8, 8, 5, 1, su2.F32)
+    assert e.value.status == su2.EINVAL
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_ensemble_create([(8, 8, 8, 8)], [-1.0], su2.HOT, 1, su2.F32)
+    assert e.value.status == su2.EINVAL
+    assert su2._lib.su2_status_str(-7).decode().startswith("non-finite")
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU path")
+def test_no_device():
+    from paper_1010_4834_amd import su2
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_create(8, 8, 8, 8, su2.COLD, 1, su2.F32)
+    assert e.value.status == su2.ENODEV

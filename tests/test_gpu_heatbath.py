@@ -1,0 +1,253 @@
+"""GPU parity of the heat-bath path against the serial FP64 oracle, through
+the C ABI (libsu2.so).
+
+FP64: one substep / one sweep from an identical configuration agrees link by
+link to 1e-12 with identical per-link try counts.  FP32 (links rounded to
+binary32, 23-bit uniforms on both sides): links agree to 1e-5 except
+downstream of accept/reject flips, whose number is reported.
+"""
+import numpy as np
+import pytest
+
+from tests import inputs, parity_util
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def su2():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1010_4834_amd import su2 as s
+    return s
+
+
+def as_f32(U):
+    return U.astype(np.float32).astype(np.float64)
+
+
+def flip_report(dims, G, O, tg, to, tol=1e-5):
+    flips = (tg != to).reshape(-1, 4)
+    down = parity_util.downstream_of_flips(dims, flips, parity_util.parity_array(dims))
+    err = np.abs(G - O).max(axis=2)
+    bad = err > tol
+    clean = err[~down]
+    return int(flips.sum()), int(bad.sum()), bool((bad & ~down).any()), \
+        float(clean.max() if clean.size else 0.0)
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 10, 6)])
+def test_hot_start(su2, orc, dims):
+    for prec, tol in ((su2.F64, 1e-14), (su2.F32, 6e-8)):
+        lat = su2.Lattice(dims, start=su2.HOT, seed=2, prec=prec)
+        G = lat.get_links()
+        O = orc.hot(dims, 2)
+        assert np.abs(G - O).max() < tol
+        lat.close()
+    lat = su2.Lattice(dims, start=su2.COLD, seed=2, prec=su2.F32)
+    assert lat.plaquette() == (1.0, 1.0, 1.0)
+    assert lat.polyakov() == 1.0
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 10, 6), (2, 2, 2, 2)])
+def test_substeps_fp64(su2, orc, dims):
+    V = int(np.prod(dims))
+    U = inputs.random_config(dims, 31)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+    lat.set_links(U)
+    lat.trace_tries(True)
+    lat.sweep = 5
+    tr = np.zeros(4 * V, np.uint32)
+    for mu in range(4):
+        for p in range(2):
+            lat.substep(2.3, 11, mu, p)
+            orc.heatbath_substep(dims, U, 2.3, 11, 5, mu, p, trace=tr)
+            G = lat.get_links()
+            assert np.abs(G - U).max() < 1e-12, (mu, p)
+    assert np.array_equal(lat.get_tries(), tr)
+    lat.close()
+
+
+@pytest.mark.parametrize("dims,beta,seed", [((8, 8, 8, 8), 2.3, 1), ((6, 4, 10, 6), 2.6, 3),
+                                            ((4, 6, 2, 8), 0.4, 9)])
+def test_sweep_fp64(su2, orc, dims, beta, seed):
+    V = int(np.prod(dims))
+    U = inputs.random_config(dims, 32)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+    lat.set_links(U)
+    lat.trace_tries(True)
+    lat.heatbath(beta, 1, seed)
+    tr = np.zeros(4 * V, np.uint32)
+    orc.heatbath_sweep(dims, U, beta, seed, 0, trace=tr)
+    assert np.array_equal(lat.get_tries(), tr)
+    assert np.abs(lat.get_links() - U).max() < 1e-12
+    tries, updates, defect = lat.stats()
+    assert updates == 4 * V and tries == int((tr & 0x7FFFFFFF).sum())
+    assert defect < 1e-14
+    lat.close()
+
+
+def test_creutz_sampler_fp64(su2, orc):
+    dims = (4, 4, 6, 4)
+    V = int(np.prod(dims))
+    U = inputs.random_config(dims, 33)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+    su2.su2_set_sampler(lat.h, su2.CREUTZ)
+    lat.set_links(U)
+    lat.trace_tries(True)
+    lat.heatbath(2.5, 1, 4)
+    tr = np.zeros(4 * V, np.uint32)
+    orc.heatbath_sweep(dims, U, 2.5, 4, 0, sampler=orc.CREUTZ, trace=tr)
+    assert np.array_equal(lat.get_tries(), tr)
+    assert np.abs(lat.get_links() - U).max() < 1e-12
+    lat.close()
+
+
+def test_c1_series_fp64(su2, orc):
+    """8^4, beta = 2.3, cold start, 20 sweeps, Philox seed 1, plaquette after
+    each sweep.  Beyond one sweep link-by-link agreement is not guaranteed in
+    principle (a flip would decorrelate); in practice the FP64 maps stay
+    within rounding, which is asserted loosely and printed."""
+    dims = (8, 8, 8, 8)
+    lat = su2.Lattice(dims, start=su2.COLD, seed=1, prec=su2.F64)
+    U = orc.cold(dims)
+    dp = []
+    for sw in range(20):
+        lat.heatbath(2.3, 1, 1)
+        orc.heatbath_sweep(dims, U, 2.3, 1, sw)
+        dp.append(abs(lat.plaquette()[0] - orc.plaquette(dims, U)[0]))
+    print("C1 |dP| per sweep:", " ".join(f"{x:.1e}" for x in dp))
+    assert max(dp) < 1e-10
+    assert np.abs(lat.get_links() - U).max() < 1e-9
+    lat.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 10, 6)])
+def test_sweep_fp32(su2, orc, dims):
+    V = int(np.prod(dims))
+    U = as_f32(inputs.random_config(dims, 34))
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F32)
+    lat.set_links(U)
+    lat.trace_tries(True)
+    lat.heatbath(2.3, 1, 5)
+    tr = np.zeros(4 * V, np.uint32)
+    orc.heatbath_sweep(dims, U, 2.3, 5, 0, ubits=23, trace=tr)
+    flips, nbad, outside, clean = flip_report(dims, lat.get_links(), U, lat.get_tries(), tr)
+    print(f"FP32 {dims}: {flips} flips, {nbad} links > 1e-5, max clean |dU| {clean:.2e}")
+    assert not outside and clean < 1e-5
+    assert flips <= max(2, V // 1000)
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_full_size_c2_one_sweep(su2, orc, prec):
+    """32^4, beta = 2.6, hot start seed 2: one sweep at the benchmark shape."""
+    dims = (32, 32, 32, 32)
+    p = getattr(su2, prec)
+    lat = su2.Lattice(dims, start=su2.HOT, seed=2, prec=p)
+    su2.su2_autotune(lat.h, 2.6)
+    print("launch", su2.su2_get_launch(lat.h))
+    U = orc.hot(dims, 2)
+    if prec == "F32":
+        U = as_f32(U)
+    lat.trace_tries(True)
+    lat.heatbath(2.6, 1, 2)
+    V = U.shape[0]
+    tr = np.zeros(4 * V, np.uint32)
+    orc.heatbath_sweep(dims, U, 2.6, 2, 0, ubits=23 if prec == "F32" else 32, trace=tr)
+    G = lat.get_links()
+    if prec == "F64":
+        assert np.array_equal(lat.get_tries(), tr)
+        assert np.abs(G - U).max() < 1e-12
+    else:
+        flips, nbad, outside, clean = flip_report(dims, G, U, lat.get_tries(), tr)
+        print(f"FP32 32^4: {flips} flips, {nbad} links > 1e-5, max clean |dU| {clean:.2e}")
+        assert not outside and clean < 1e-5
+    P = lat.plaquette()
+    Po = orc.plaquette(dims, U)
+    assert abs(P[0] - Po[0]) < (1e-13 if prec == "F64" else 1e-6)
+    lat.close()
+
+
+def test_launch_shapes_bitwise(su2, orc):
+    """FP64 links do not depend on the launch shape, the XCD remap or graph
+    replay."""
+    import os
+    dims = (6, 4, 10, 6)
+    U = inputs.random_config(dims, 35)
+    ref = None
+    for block, grid, remap in ((256, 0, 1), (64, 0, 0), (128, 16, 1), (192, 8, 0), (64, 24, 1)):
+        lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+        su2.su2_set_launch(lat.h, block, grid, remap)
+        lat.set_links(U)
+        lat.heatbath(2.4, 3, 6)
+        G = lat.get_links()
+        if ref is None:
+            ref = G
+        assert np.array_equal(G, ref), (block, grid, remap)
+        lat.close()
+    os.environ["SU2_NO_GRAPH"] = "1"
+    try:
+        lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+        lat.set_links(U)
+        lat.heatbath(2.4, 3, 6)
+        assert np.array_equal(lat.get_links(), ref)
+        lat.close()
+    finally:
+        del os.environ["SU2_NO_GRAPH"]
+
+
+def test_overrelax_fp64(su2, orc):
+    dims = (6, 4, 4, 8)
+    U = inputs.random_config(dims, 36)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+    lat.set_links(U)
+    p0 = lat.plaquette()[0]
+    lat.overrelax(2)
+    orc.overrelax_sweep(dims, U)
+    orc.overrelax_sweep(dims, U)
+    assert np.abs(lat.get_links() - U).max() < 1e-12
+    assert abs(lat.plaquette()[0] - p0) < 1e-13
+    lat.close()
+
+
+def test_resume_bitwise(su2, tmp_path):
+    dims = (4, 6, 4, 6)
+    for prec in (su2.F64, su2.F32):
+        a = su2.Lattice(dims, start=su2.HOT, seed=8, prec=prec)
+        a.heatbath(2.5, 4, 8)
+        b = su2.Lattice(dims, start=su2.HOT, seed=8, prec=prec)
+        b.heatbath(2.5, 2, 8)
+        path = str(tmp_path / "ck.su2")
+        su2.su2_save(b.h, path)
+        b.close()
+        h = su2.su2_load(path)
+        assert su2.su2_get_sweep(h) == 2
+        su2.su2_heatbath(h, 2.5, 2, 8)
+        assert np.array_equal(su2.su2_get_links(h, a.volume), a.get_links())
+        su2.su2_destroy(h)
+        a.close()
+
+
+def test_errors(su2):
+    dims = (4, 4, 4, 4)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F32)
+    bad = np.zeros((256, 4, 4))
+    with pytest.raises(su2.SU2Error) as e:
+        lat.set_links(bad)
+    assert e.value.status == su2.EINVAL
+    for args in ((-1.0, 1, 1), (float("nan"), 1, 1), (2.0, -1, 1)):
+        with pytest.raises(su2.SU2Error) as e:
+            lat.heatbath(*args)
+        assert e.value.status == su2.EINVAL
+    with pytest.raises(su2.SU2Error):
+        lat.wilson_loops(5, 2)
+    with pytest.raises(su2.SU2Error):
+        su2.su2_set_launch(lat.h, 100, 0, 1)
+    with pytest.raises(su2.SU2Error) as e:
+        lat.get_smeared()
+    assert e.value.status == su2.ESTATE
+    lat.heatbath(0.0, 2, 3)           # beta = 0: Haar draws, no hang
+    assert lat.stats()[2] < 1e-6
+    lat.close()

@@ -1,0 +1,76 @@
+"""GPU parity of the measurements (plaquette, Polyakov loop, APE smearing,
+Wilson loops) against the oracle on identical uploaded configurations.
+FP64 to 1e-13 (1e-12 after many APE steps); FP32 links (binary32 traces,
+binary64 compensated sums) to 1e-5 (2e-5 for Wilson loops and smeared
+links, whose traces chain up to 2(R+T) binary32 products)."""
+import numpy as np
+import pytest
+
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def su2():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1010_4834_amd import su2 as s
+    return s
+
+
+DIMS = [(4, 4, 4, 4), (6, 4, 10, 6), (8, 6, 4, 12), (2, 2, 2, 2)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_plaquette_polyakov(su2, orc, dims):
+    U = inputs.random_config(dims, 41)
+    U32 = U.astype(np.float32).astype(np.float64)
+    for prec, ref, tol in ((su2.F64, U, 1e-13), (su2.F32, U32, 1e-6)):
+        lat = su2.Lattice(dims, start=su2.COLD, prec=prec)
+        lat.set_links(ref)
+        P = lat.plaquette()
+        Po = orc.plaquette(dims, ref)
+        assert np.abs(np.array(P) - np.array(Po)).max() < tol, (prec, P, Po)
+        assert abs(lat.polyakov() - orc.polyakov(dims, ref)) < tol
+        lat.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 6), (6, 4, 10, 6), (2, 4, 2, 4)])
+def test_ape_and_wilson(su2, orc, dims):
+    U = inputs.random_config(dims, 42)
+    U32 = U.astype(np.float32).astype(np.float64)
+    Rm, Tm = min(dims[:3]), min(dims[3], 5)
+    for prec, ref, tl, tw in ((su2.F64, U, 1e-12, 1e-13), (su2.F32, U32, 2e-5, 2e-5)):
+        lat = su2.Lattice(dims, start=su2.COLD, prec=prec)
+        lat.set_links(ref)
+        W = lat.wilson_loops(Rm, Tm)
+        assert np.abs(W - orc.wilson(dims, ref, Rm, Tm)).max() < tw
+        assert abs(W[0, 0] - lat.plaquette()[2]) < 1e-6
+        lat.ape_smear(0.7, 5)
+        S = lat.get_smeared()
+        So = orc.ape(dims, ref, 0.7, 5)
+        assert np.abs(S - So).max() < tl
+        Ws = lat.wilson_loops(Rm, Tm)
+        assert np.abs(Ws - orc.wilson(dims, ref, Rm, Tm, So)).max() < tw
+        # a heat-bath sweep drops the smeared links
+        lat.heatbath(2.5, 1, 1)
+        with pytest.raises(su2.SU2Error):
+            lat.get_smeared()
+        lat.close()
+
+
+def test_c4_full_size_sampled(su2, orc):
+    """24^3 x 48, beta = 2.5, hot start seed 4: APE alpha = 0.7 x 25 on the
+    spatial links, W(R <= 12, T <= 16); sampled (R, T) against the oracle."""
+    dims = (24, 24, 24, 48)
+    U = orc.hot(dims, 4)
+    lat = su2.Lattice(dims, start=su2.HOT, seed=4, prec=su2.F64)
+    assert np.abs(lat.get_links() - U).max() < 1e-14
+    lat.ape_smear(0.7, 25)
+    W = lat.wilson_loops(12, 16)
+    S = orc.ape(dims, U, 0.7, 25)
+    assert np.abs(lat.get_smeared() - S).max() < 1e-11
+    for R, T in ((1, 1), (2, 3), (12, 16)):
+        assert abs(W[R - 1, T - 1] - orc.wilson_rt(dims, U, R, T, S)) < 1e-13, (R, T)
+    lat.close()
