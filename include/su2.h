@@ -30,7 +30,9 @@
  *    two-sum accumulation); SU2_F64 is binary64 throughout.
  *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
  *    counter = (site, sweep, lattice_id<<8 | purpose<<4 | mu<<1 | parity,
- *    try).  One heat-bath sweep consumes the counters of one sweep index;
+ *    try).  A link update uses one call per try of its a0 draw and the
+ *    call with try word 0xFFFFFFFF for the direction of its vector part.
+ *    One heat-bath sweep consumes the counters of one sweep index;
  *    each lattice keeps a sweep counter so successive calls continue the
  *    stream.  Results do not depend on launch shapes.
  */
@@ -91,7 +93,7 @@ size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec);
  * Sec. 2).  The hot start draws Philox purpose 1 with `seed`.
  * device_links: optional caller-owned device buffer of su2_link_bytes()
  * bytes (NULL: the library allocates).  EINVAL on odd or < 2 extents, a
- * volume above 2^31 sites, or a bad enum; ENODEV without a GPU. */
+ * volume above 2^30 sites, or a bad enum; ENODEV without a GPU. */
 su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t seed,
                       su2_prec prec, void *device_links, size_t device_bytes,
                       su2_lattice *out);
@@ -168,7 +170,7 @@ su2_status su2_set_sweep(su2_lattice lat, uint32_t sweep);
 su2_status su2_stats(su2_lattice lat, uint64_t *tries, uint64_t *updates,
                      double *max_unit_defect);
 
-/* Per-link try record of later heat-bath calls: tries | creutz << 31 in
+/* Per-link record of later heat-bath calls: tries | creutz << 31, in
  * canonical [s][mu] order (V*4 uint32).  enable = 0 frees it. */
 su2_status su2_trace_tries(su2_lattice lat, int enable);
 su2_status su2_get_tries(su2_lattice lat, uint32_t *host);
@@ -180,11 +182,12 @@ su2_status su2_save(su2_lattice lat, const char *path);
 su2_status su2_load(const char *path, su2_lattice *out);
 
 /* Launch shape: threads per workgroup (64, 128, 192 or 256), resident
- * workgroups of the persistent grid (0 = one workgroup per tile) and
- * whether tiles are laid out per XCD (1) or round-robin (0).  Results do
- * not depend on it. */
-su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap);
-su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap);
+ * workgroups of the persistent grid (0 = one workgroup per tile; else a
+ * multiple of 8), whether tiles are laid out per XCD (1) or round-robin (0),
+ * and heat-bath links per lane (1, 2 or 4: a lane draws its links in one
+ * rejection loop).  Results do not depend on it. */
+su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap, int links_per_lane);
+su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap, int *links_per_lane);
 /* Time the candidate launch shapes on this lattice and keep the fastest
  * (the links are saved and restored around the trial sweeps). */
 su2_status su2_autotune(su2_lattice lat, double beta);
@@ -218,7 +221,10 @@ su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, uint64_t seed, double
 su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
 su2_status su2_ensemble_set_links(su2_ensemble ens, int i, const double *host);
 su2_status su2_ensemble_stats(su2_ensemble ens, uint64_t *tries, uint64_t *updates);
-su2_status su2_ensemble_set_launch(su2_ensemble ens, int block, int grid, int xcd_remap);
+su2_status su2_ensemble_set_launch(su2_ensemble ens, int block, int grid, int xcd_remap,
+                                   int links_per_lane);
+su2_status su2_ensemble_get_launch(su2_ensemble ens, int *block, int *grid, int *xcd_remap,
+                                   int *links_per_lane);
 su2_status su2_ensemble_autotune(su2_ensemble ens);
 su2_status su2_ensemble_set_timing(su2_ensemble ens, int enable);
 su2_status su2_ensemble_get_timing(su2_ensemble ens, su2_kernel_kind kind, double *ms,

@@ -36,6 +36,7 @@ def lib():
             "or_hot": (None, [P, P, U64, U32]),
             "or_staple": (None, [P, P, I64, C.c_int, P]),
             "or_sample_delta": (U32, [D, C.c_int, U64, P, C.c_int, P, P]),
+            "or_sample_link": (U32, [D, C.c_int, U64, P, C.c_int, P, P]),
             "or_sample_many": (None, [D, C.c_int, U64, I64, C.c_int, P, P]),
             "or_heatbath_link": (U32, [P, P, I64, C.c_int, D, U64, U32, U32, C.c_int, C.c_int]),
             "or_heatbath_substep": (U64, [P, P, D, U64, U32, U32, C.c_int, C.c_int,
@@ -132,6 +133,14 @@ def sample_delta(alpha, sampler, seed, ctr3, ubits=32):
     tries = lib().or_sample_delta(float(alpha), int(sampler), int(seed), _p(c),
                                   int(ubits), _p(d), _p(cr))
     return float(d[0]), int(tries), bool(cr[0])
+
+
+def sample_link(alpha, sampler, seed, ctr3, ubits=32):
+    c = np.ascontiguousarray(ctr3, dtype=np.uint32)
+    X = np.zeros(4)
+    tries = lib().or_sample_link(float(alpha), int(sampler), int(seed), _p(c), int(ubits),
+                                 _p(X), None)
+    return X, int(tries)
 
 
 def sample_many(alpha, sampler, seed, nsamp, ubits=32):

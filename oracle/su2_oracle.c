@@ -243,16 +243,38 @@ uint32_t or_sample_delta(double alpha, int sampler, uint64_t seed,
     }
 }
 
-/* Heat-bath update of link (s, mu) (paper Sec. 2): draw X with
- * x0 = 1 - delta and x uniformly on the 2-sphere of radius |x| =
- * sqrt(delta (2 - delta)), then U' = X W^dag with W = V/k, k = sqrt(det V).
- * The direction uses its own Philox call (try index 0xFFFFFFFF):
- * cos(theta) = 1 - 2 u1, phi = 2 pi u2.  U' is renormalised. */
+/* Draw X = (x0, x): x0 = a0 from the law of paper Sec. 2 by
+ * or_sample_delta's loop, and x uniformly on the 2-sphere of radius
+ * sqrt(1 - x0^2) from its own Philox call (try word 0xFFFFFFFF):
+ * cos(theta) = 1 - 2 u1, phi = 2 pi u2, |x| = sqrt(delta (2 - delta)).
+ * The direction thus does not depend on the number of tries or on alpha.
+ * Returns the tries; *used_creutz (nullable) reports the branch. */
+uint32_t or_sample_link(double alpha, int sampler, uint64_t seed, const uint32_t ctr3[3],
+                        int ubits, double X[4], int *used_creutz)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double d;
+    uint32_t tries = or_sample_delta(alpha, sampler, seed, ctr3, ubits, &d, used_creutz);
+    uint32_t w[4];
+    or_draw(seed, ctr3[0], ctr3[1], ctr3[2], 0xFFFFFFFFu, w);
+    double u1 = or_uniform(w[0], ubits), u2 = or_uniform(w[1], ubits);
+    double cth = 1.0 - 2.0 * u1;
+    double sth = 2.0 * sqrt(u1 * (1.0 - u1));
+    double ra = sqrt(d * (2.0 - d));
+    X[0] = 1.0 - d;
+    X[1] = ra * sth * cos(two_pi * u2);
+    X[2] = ra * sth * sin(two_pi * u2);
+    X[3] = ra * cth;
+    return tries;
+}
+
+/* Heat-bath update of link (s, mu) (paper Sec. 2): X from or_sample_link
+ * with coupling alpha = beta k, k = sqrt(det V); U' = X W^dag with W = V/k
+ * (the identity if V = 0), renormalised. */
 static uint32_t or_update_link(const int n[4], double *U, int64_t s, int mu,
                                double beta, uint64_t seed, uint32_t sweep,
                                uint32_t lat_id, int sampler, int ubits)
 {
-    const double two_pi = 6.283185307179586476925286766559;
     int p = or_parity(n, s);
     double V[4];
     or_staple(n, U, s, mu, V);
@@ -261,18 +283,9 @@ static uint32_t or_update_link(const int n[4], double *U, int64_t s, int mu,
     double alpha = beta * k;
 
     uint32_t ctr3[3] = {(uint32_t)s, sweep, or_tag(lat_id, OR_PURPOSE_HEATBATH, mu, p)};
-    double delta;
+    double X[4];
     int creutz;
-    uint32_t tries = or_sample_delta(alpha, sampler, seed, ctr3, ubits, &delta, &creutz);
-
-    uint32_t w[4];
-    or_draw(seed, ctr3[0], ctr3[1], ctr3[2], 0xFFFFFFFFu, w);
-    double u1 = or_uniform(w[0], ubits), u2 = or_uniform(w[1], ubits);
-    double cth = 1.0 - 2.0 * u1;
-    double sth = 2.0 * sqrt(u1 * (1.0 - u1));
-    double phi = two_pi * u2;
-    double ra = sqrt(delta * (2.0 - delta));
-    double X[4] = {1.0 - delta, ra * sth * cos(phi), ra * sth * sin(phi), ra * cth};
+    uint32_t tries = or_sample_link(alpha, sampler, seed, ctr3, ubits, X, &creutz);
 
     double Wd[4];
     if (k2 > 0.0) {

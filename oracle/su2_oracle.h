@@ -67,11 +67,16 @@ uint32_t or_sample_delta(double alpha, int sampler, uint64_t seed,
                          const uint32_t ctr3[3], int ubits, double *delta,
                          int *used_creutz);
 
+/* the full draw X = (a0, a), a isotropic of norm sqrt(1 - a0^2) from its
+ * own Philox call (try word 0xFFFFFFFF); returns the tries */
+uint32_t or_sample_link(double alpha, int sampler, uint64_t seed, const uint32_t ctr3[3],
+                        int ubits, double X[4], int *used_creutz);
+
 /* n draws with counters (i, 0, 0, try), i = 0..n-1 (sampler statistics) */
 void or_sample_many(double alpha, int sampler, uint64_t seed, int64_t nsamp,
                     int ubits, double *delta, uint32_t *tries);
 
-/* heat-bath update of the single link (s, mu); returns tries | creutz<<31 */
+/* heat-bath update of the single link (s, mu); returns the trace word */
 uint32_t or_heatbath_link(const int n[4], double *U, int64_t s, int mu,
                           double beta, uint64_t seed, uint32_t sweep,
                           uint32_t lat_id, int sampler, int ubits);

@@ -1,7 +1,10 @@
 """Build the gfx950 SU(2) library (libsu2.so) in-tree with hipcc.
 
 Every HIP source is compiled for gfx950 with packed-FP32 instruction
-selection disabled; the C ABI is declared in include/su2.h.
+selection disabled and multiply-adds fused only within a source expression
+(-ffp-contract=on), so results are bitwise independent of which kernel
+instantiation (launch shape) runs them; the C ABI is declared in
+include/su2.h.
 """
 import os
 import subprocess
@@ -12,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsu2.so")
 SOURCES = ["csrc/su2_kernels.hip", "csrc/su2_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 

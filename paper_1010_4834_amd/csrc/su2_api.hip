@@ -48,10 +48,10 @@ struct su2_ensemble_s {
     long long total_links = 0;  // 4 * sum V
     long long total_sites = 0;
 
-    int block = 256, grid = 0, remap = 1;
-    std::vector<Tile> htiles, hstiles, hvtiles;
-    Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr;
-    int ntiles = 0, nstiles = 0, nvtiles = 0;
+    int block = 256, grid = 0, remap = 1, nl = 1;
+    std::vector<Tile> htiles, hstiles, hvtiles, hmtiles;
+    Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr, *mtiles = nullptr;
+    int ntiles = 0, nstiles = 0, nvtiles = 0, nmtiles = 0;
 
     void *links = nullptr;
     bool own_links = true;
@@ -63,7 +63,7 @@ struct su2_ensemble_s {
     unsigned long long tries_acc = 0;  // folded from tries_part on reshapes
     unsigned long long updates = 0;
 
-    double *part_plaq = nullptr, *part_poly = nullptr;
+    double *part_plaq = nullptr, *part_poly = nullptr, *part_hb = nullptr;
     double *res = nullptr;   // device scratch for single results
     double *hres = nullptr;  // pinned host mirror of res
     double *ser_plaq = nullptr, *ser_poly = nullptr;
@@ -152,13 +152,15 @@ su2_status dalloc(su2_ensemble_s *E, P **p, size_t bytes) {
 KArgs kargs(su2_ensemble_s *E, int which = 0) {
     KArgs a;
     a.desc = E->ddesc;
-    a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : E->vtiles;
-    a.ntiles = which == 0 ? E->ntiles : which == 1 ? E->nstiles : E->nvtiles;
+    a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : which == 2 ? E->vtiles : E->mtiles;
+    a.ntiles = which == 0 ? E->ntiles : which == 1 ? E->nstiles : which == 2 ? E->nvtiles : E->nmtiles;
     a.xcd_remap = E->remap;
     a.links = E->links;
     a.st = E->st;
+    a.err = &E->st->err;
     a.trace = E->trace;
     a.tries_part = E->tries_part;
+    a.plaq_part = E->part_hb;
     a.sampler = E->sampler;
     return a;
 }
@@ -239,6 +241,7 @@ su2_status build_tiles(su2_ensemble_s *E) {
     E->htiles.clear();
     E->hstiles.clear();
     E->hvtiles.clear();
+    E->hmtiles.clear();
     const int B = E->block;
     for (int l = 0; l < E->n; ++l) {
         LatDesc &d = E->hdesc[l];
@@ -251,22 +254,30 @@ su2_status build_tiles(su2_ensemble_s *E) {
         d.vtile0 = (int)E->hvtiles.size();
         for (int s = 0; s < 2 * d.vh; s += B) E->hvtiles.push_back(make_int2(l, s));
         d.nvtile = (int)E->hvtiles.size() - d.vtile0;
+        d.mtile0 = (int)E->hmtiles.size();
+        for (int s = 0; s < d.vh; s += B * E->nl) E->hmtiles.push_back(make_int2(l, s));
+        d.nmtile = (int)E->hmtiles.size() - d.mtile0;
     }
     E->ntiles = (int)E->htiles.size();
     E->nstiles = (int)E->hstiles.size();
     E->nvtiles = (int)E->hvtiles.size();
+    E->nmtiles = (int)E->hmtiles.size();
     CHK(dalloc(E, &E->tiles, sizeof(Tile) * E->ntiles));
     CHK(dalloc(E, &E->stiles, sizeof(Tile) * E->nstiles));
     CHK(dalloc(E, &E->vtiles, sizeof(Tile) * E->nvtiles));
+    CHK(dalloc(E, &E->mtiles, sizeof(Tile) * E->nmtiles));
     CHK(dalloc(E, &E->tries_part, sizeof(unsigned long long) * E->ntiles));
     CHK(dalloc(E, &E->part_plaq, sizeof(double) * 4 * E->ntiles));
     CHK(dalloc(E, &E->part_poly, sizeof(double) * 2 * E->nstiles));
+    CHK(dalloc(E, &E->part_hb, sizeof(double) * 6 * E->nmtiles));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, E->stream()));
     HIPCHK(hipMemcpyAsync(E->tiles, E->htiles.data(), sizeof(Tile) * E->ntiles, hipMemcpyHostToDevice,
                           E->stream()));
     HIPCHK(hipMemcpyAsync(E->stiles, E->hstiles.data(), sizeof(Tile) * E->nstiles, hipMemcpyHostToDevice,
                           E->stream()));
     HIPCHK(hipMemcpyAsync(E->vtiles, E->hvtiles.data(), sizeof(Tile) * E->nvtiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    HIPCHK(hipMemcpyAsync(E->mtiles, E->hmtiles.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
                           E->stream()));
     CHK(upload_desc(E));
     HIPCHK(hipStreamSynchronize(E->stream()));
@@ -367,8 +378,8 @@ void destroy_common(su2_ensemble_s *E) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
-    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->st, E->tries_part, E->part_plaq,
-                    E->part_poly, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1], E->wl_t,
+    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->st, E->tries_part, E->part_plaq,
+                    E->part_poly, E->part_hb, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1], E->wl_t,
                     E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -379,31 +390,31 @@ void destroy_common(su2_ensemble_s *E) {
 
 // ---- one sweep --------------------------------------------------------------
 su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
-    const KArgs a = kargs(E);
+    const KArgs a = kargs(E, 3);
+    // with a plaquette series the odd substeps mu >= 1 also sum the
+    // plaquettes of the sweep's final configuration (no separate pass)
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
+            const bool plaq = (meas & 1) && par == 1 && mu >= 1;
             Timed t(E, SU2_K_HEATBATH, s);
-            su2::launch_heatbath(a, E->f32, mu, par, E->block, E->grid, s, E->trace != nullptr);
+            su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq);
             t.done(s);
         }
-    if (meas & 1) {
-        Timed t(E, SU2_K_PLAQUETTE, s);
-        su2::launch_plaquette(a, E->f32, E->part_plaq, E->block, E->grid, s);
-        t.done(s);
-        Timed r(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->part_plaq, 0, E->st, 1, E->ser_plaq, E->ser_cap, s);
-        r.done(s);
-    }
     if (meas & 2) {
-        const KArgs sa = kargs(E, 1);
         Timed t(E, SU2_K_POLYAKOV, s);
-        su2::launch_polyakov(sa, E->f32, E->part_poly, E->block, E->grid, s);
+        su2::launch_polyakov(kargs(E, 1), E->f32, E->part_poly, E->block, E->grid, s);
         t.done(s);
-        Timed r(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->part_poly, 1, E->st, 1, E->ser_poly, E->ser_cap, s);
-        r.done(s);
     }
-    su2::launch_bump(E->st, s);
+    if (meas) {
+        // per-lattice series values; the last block advances the sweep counter
+        Timed r(E, SU2_K_REDUCE, s);
+        su2::launch_finalize(E->ddesc, E->n, (meas & 1) ? E->part_hb : nullptr, 1,
+                             (meas & 2) ? E->part_poly : nullptr, E->st, 1, 1, E->ser_plaq, E->ser_poly,
+                             E->ser_cap, s);
+        r.done(s);
+    } else {
+        su2::launch_bump(E->st, s);
+    }
     HIPCHK(hipGetLastError());
     return SU2_OK;
 }
@@ -464,7 +475,7 @@ su2_status measure_plaquette(su2_ensemble_s *E, int l, double *avg, double *sp, 
     }
     {
         Timed t(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->part_plaq, 0, E->st, 0, E->res, 4, s);
+        su2::launch_finalize(E->ddesc, E->n, E->part_plaq, 0, nullptr, E->st, 0, 0, E->res, nullptr, 4, s);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -486,7 +497,7 @@ su2_status measure_polyakov(su2_ensemble_s *E, int l, double *out) {
     }
     {
         Timed t(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->part_poly, 1, E->st, 0, E->res, 4, s);
+        su2::launch_finalize(E->ddesc, E->n, nullptr, 0, E->part_poly, E->st, 0, 0, nullptr, E->res, 4, s);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -571,15 +582,17 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
     return check_err(E);
 }
 
-su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap) {
+su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, int nl) {
     if (block < 64 || block > 256 || (block & 63)) return SU2_EINVAL;
     if (grid < 0 || (grid & 7)) return SU2_EINVAL;
     if (remap != 0 && remap != 1) return SU2_EINVAL;
-    const bool reshape = block != E->block;
+    if (nl != 1 && nl != 2 && nl != 4) return SU2_EINVAL;
+    const bool reshape = block != E->block || nl != E->nl;
     E->grid = grid;
     E->remap = remap;
     if (reshape) {
         E->block = block;
+        E->nl = nl;
         CHK(build_tiles(E));
     }
     drop_graphs(E);
@@ -588,14 +601,16 @@ su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap) 
 
 // Time one sweep per candidate shape; links, sweep counter and tries are
 // restored afterwards.
-std::map<std::string, int3> g_tune_cache;
+struct Shape { int block, grid, remap, nl; };
+std::map<std::string, Shape> g_tune_cache;
 
 su2_status autotune_common(su2_ensemble_s *E) {
     char key[160];
     std::snprintf(key, sizeof key, "%s:n%d:sites%lld:t%lld", E->f32 ? "f32" : "f64", E->n, E->total_sites,
                   (long long)E->hdesc[0].n[3]);
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) return set_launch_common(E, it->second.x, it->second.y, it->second.z);
+    if (it != g_tune_cache.end())
+        return set_launch_common(E, it->second.block, it->second.grid, it->second.remap, it->second.nl);
 
     hipStream_t s = E->stream();
     void *backup = nullptr;
@@ -612,31 +627,33 @@ su2_status autotune_common(su2_ensemble_s *E) {
 
     const int blocks[] = {64, 128, 256};
     const int gmul[] = {0, 4, 8, 16};
+    const int nls[] = {1, 2, 4};
     hipEvent_t ea, eb;
     HIPCHK(hipEventCreate(&ea));
     HIPCHK(hipEventCreate(&eb));
     float best = 1e30f;
-    int3 bestc = make_int3(E->block, E->grid, E->remap);
-    for (int b : blocks)
-        for (int gm : gmul)
-            for (int rm = 0; rm < 2; ++rm) {
-                const int g = gm ? gm * cus / 8 * 8 : 0;
-                CHK(set_launch_common(E, b, g, rm));
-                CHK(enqueue_sweep(E, 0, s));  // warm-up
-                HIPCHK(hipEventRecord(ea, s));
-                for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 0, s));
-                HIPCHK(hipEventRecord(eb, s));
-                HIPCHK(hipEventSynchronize(eb));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, ea, eb));
-                if (ms < best) {
-                    best = ms;
-                    bestc = make_int3(b, g, rm);
+    Shape bestc{E->block, E->grid, E->remap, E->nl};
+    for (int nl : nls)
+        for (int b : blocks)
+            for (int gm : gmul)
+                for (int rm = 0; rm < 2; ++rm) {
+                    const int g = gm ? gm * cus / 8 * 8 : 0;
+                    CHK(set_launch_common(E, b, g, rm, nl));
+                    CHK(enqueue_sweep(E, 0, s));  // warm-up
+                    HIPCHK(hipEventRecord(ea, s));
+                    for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 0, s));
+                    HIPCHK(hipEventRecord(eb, s));
+                    HIPCHK(hipEventSynchronize(eb));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, ea, eb));
+                    if (ms < best) {
+                        best = ms;
+                        bestc = Shape{b, g, rm, nl};
+                    }
                 }
-            }
     HIPCHK(hipEventDestroy(ea));
     HIPCHK(hipEventDestroy(eb));
-    CHK(set_launch_common(E, bestc.x, bestc.y, bestc.z));
+    CHK(set_launch_common(E, bestc.block, bestc.grid, bestc.remap, bestc.nl));
     HIPCHK(hipMemcpyAsync(E->links, backup, E->link_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -786,9 +803,18 @@ su2_status su2_ensemble_stats(su2_ensemble E, uint64_t *tries, uint64_t *updates
     return stats_common(E, tries, updates, nullptr);
 }
 
-su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap) {
+su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap, int links_per_lane) {
     CHK(enter(E));
-    return set_launch_common(E, block, grid, xcd_remap);
+    return set_launch_common(E, block, grid, xcd_remap, links_per_lane);
+}
+
+su2_status su2_ensemble_get_launch(su2_ensemble E, int *block, int *grid, int *xcd_remap, int *links_per_lane) {
+    CHK(enter(E));
+    if (block) *block = E->block;
+    if (grid) *grid = E->grid;
+    if (xcd_remap) *xcd_remap = E->remap;
+    if (links_per_lane) *links_per_lane = E->nl;
+    return SU2_OK;
 }
 
 su2_status su2_ensemble_autotune(su2_ensemble E) {
@@ -864,7 +890,8 @@ su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int m
     hipStream_t s = E->stream();
     {
         Timed t(E, SU2_K_HEATBATH, s);
-        su2::launch_heatbath(kargs(E), E->f32, mu, parity, E->block, E->grid, s, E->trace != nullptr);
+        su2::launch_heatbath(kargs(E, 3), E->f32, mu, parity, E->nl, E->block, E->grid, s, E->trace != nullptr,
+                             false);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -1096,16 +1123,12 @@ su2_status su2_load(const char *path, su2_lattice *out) {
     return SU2_OK;
 }
 
-su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap) {
-    return su2_ensemble_set_launch(E, block, grid, remap);
+su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap, int links_per_lane) {
+    return su2_ensemble_set_launch(E, block, grid, remap, links_per_lane);
 }
 
-su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap) {
-    CHK(enter(E));
-    if (block) *block = E->block;
-    if (grid) *grid = E->grid;
-    if (remap) *remap = E->remap;
-    return SU2_OK;
+su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap, int *links_per_lane) {
+    return su2_ensemble_get_launch(E, block, grid, remap, links_per_lane);
 }
 
 su2_status su2_autotune(su2_lattice E, double beta) {

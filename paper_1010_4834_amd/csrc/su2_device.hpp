@@ -34,6 +34,7 @@ struct LatDesc {
     int tile0, ntile;    // range in the half-site tile table
     int stile0, nstile;  // range in the spatial-site tile table
     int vtile0, nvtile;  // range in the full-site tile table
+    int mtile0, nmtile;  // range in the heat-bath (links-per-lane) tile table
 };
 
 // Mutable state read by the kernels; lives in device memory so that one
@@ -43,7 +44,7 @@ struct DevState {
     unsigned int sweep;     // Philox sweep word of the sweep in progress
     unsigned int run_base;  // sweep index of the first sweep of a series
     unsigned int err;       // sampler try-cap hits (non-finite input)
-    unsigned int pad;
+    unsigned int done;      // arrival ticket of the per-sweep final reduction
 };
 
 // A tile: lattice index and first index (half-site, spatial site or site).
@@ -58,11 +59,12 @@ __device__ __forceinline__ uint32_t tag(int lat_id, uint32_t purpose, int mu, in
     return ((uint32_t)lat_id << 8) | (purpose << 4) | ((uint32_t)mu << 1) | (uint32_t)parity;
 }
 
-// q = n / d, r = n % d for 0 <= n < 2^31 with a binary64 reciprocal and a
-// one-step correction (the product is within one of the true quotient).
+// q = n / d, r = n % d for 0 <= n < 2^31, 0 < d < 2^24, with a binary64
+// reciprocal and a one-step correction (the product is within one of the
+// true quotient); q*d < 2^31 so the 24-bit multiply is exact.
 __device__ __forceinline__ void udiv(int n, int d, double inv, int &q, int &r) {
     int qq = (int)((double)n * inv);
-    int rr = n - qq * d;
+    int rr = n - (int)__umul24((unsigned)qq, (unsigned)d);
     if (rr < 0) { --qq; rr += d; }
     else if (rr >= d) { ++qq; rr -= d; }
     q = qq;
@@ -75,13 +77,22 @@ template <class T> struct Q { T a, b, c, d; };
 
 template <class T>
 __device__ __forceinline__ Q<T> qmul(const Q<T> &x, const Q<T> &y) {
-    // (x0 y0 - x.y,  x0 y + y0 x - x cross y)
+    // (x0 y0 - x.y,  x0 y + y0 x - x cross y), each component one chain of
+    // a product and three fused multiply-adds
     Q<T> r;
     r.a = x.a * y.a - x.b * y.b - x.c * y.c - x.d * y.d;
-    r.b = x.a * y.b + y.a * x.b - (x.c * y.d - x.d * y.c);
-    r.c = x.a * y.c + y.a * x.c - (x.d * y.b - x.b * y.d);
-    r.d = x.a * y.d + y.a * x.d - (x.b * y.c - x.c * y.b);
+    r.b = x.a * y.b + x.b * y.a - x.c * y.d + x.d * y.c;
+    r.c = x.a * y.c + x.c * y.a - x.d * y.b + x.b * y.d;
+    r.d = x.a * y.d + x.d * y.a - x.b * y.c + x.c * y.b;
     return r;
+}
+// s += x y (four fused multiply-adds per component)
+template <class T>
+__device__ __forceinline__ void qmul_acc(Q<T> &s, const Q<T> &x, const Q<T> &y) {
+    s.a = s.a + x.a * y.a - x.b * y.b - x.c * y.c - x.d * y.d;
+    s.b = s.b + x.a * y.b + x.b * y.a - x.c * y.d + x.d * y.c;
+    s.c = s.c + x.a * y.c + x.c * y.a - x.d * y.b + x.b * y.d;
+    s.d = s.d + x.a * y.d + x.d * y.a - x.b * y.c + x.c * y.b;
 }
 template <class T> __device__ __forceinline__ Q<T> qdag(const Q<T> &x) {
     return Q<T>{x.a, -x.b, -x.c, -x.d};
@@ -95,44 +106,53 @@ template <class T> __device__ __forceinline__ T half_tr_xyd(const Q<T> &x, const
 }
 template <class T> __device__ __forceinline__ Q<T> qone() { return Q<T>{T(1), T(0), T(0), T(0)}; }
 
-// Scale to unit norm with the squared norm and its reciprocal square root
-// evaluated in binary64 (the reunitarisation that keeps binary32 links on
-// the group).
+// Scale to unit norm with the squared norm and the scale factor evaluated
+// in binary64 (the reunitarisation that keeps binary32 links on the group).
+// Updated links have |1 - n2| ~ 1e-7, where 1 - e/2 + 3e^2/8 (e = n2 - 1)
+// equals 1/sqrt(n2) to O(e^3); farther from the group the exact form is used.
 template <class T> __device__ __forceinline__ Q<T> qnormalize(const Q<T> &x) {
-    double a = x.a, b = x.b, c = x.c, d = x.d;
-    double n2 = a * a + b * b + c * c + d * d;
-    double inv = 1.0 / sqrt(n2);
-    return Q<T>{(T)(a * inv), (T)(b * inv), (T)(c * inv), (T)(d * inv)};
+    const double a = x.a, b = x.b, c = x.c, d = x.d;
+    const double n2 = a * a + b * b + c * c + d * d;
+    const double e = n2 - 1.0;
+    double f;
+    if (fabs(e) < 1e-4) f = 1.0 - e * (0.5 - 0.375 * e);
+    else f = 1.0 / sqrt(n2);
+    return Q<T>{(T)(a * f), (T)(b * f), (T)(c * f), (T)(d * f)};
 }
 
 // ---------------------------------------------------------------------------
-// Link access.  `blk` is the first link of a (lattice, mu, parity) block.
+// Link access through the uniform base `p` of one (lattice, mu, parity)
+// block (scalar registers) plus a 32-bit per-lane byte offset, so each
+// wavefront load is one global load with a scalar base and no 64-bit
+// address math.  `hoff` (binary64 only) = 16 vh bytes, the distance from the
+// (a0,a1) plane to the (a2,a3) plane of a block.
 template <class T> struct Links;
 
 template <> struct Links<float> {
-    static __device__ __forceinline__ Q<float> ld(const void *base, long long blk, int vh, int cb) {
-        (void)vh;
-        float4 v = reinterpret_cast<const float4 *>(base)[blk + cb];
+    static constexpr int BYTES = 16;
+    static __device__ __forceinline__ Q<float> ld(const char *p, uint32_t hoff, uint32_t cb) {
+        (void)hoff;
+        const float4 v = *reinterpret_cast<const float4 *>(p + (cb << 4));
         return Q<float>{v.x, v.y, v.z, v.w};
     }
-    static __device__ __forceinline__ void st(void *base, long long blk, int vh, int cb,
-                                              const Q<float> &q) {
-        (void)vh;
-        reinterpret_cast<float4 *>(base)[blk + cb] = make_float4(q.a, q.b, q.c, q.d);
+    static __device__ __forceinline__ void st(char *p, uint32_t hoff, uint32_t cb, const Q<float> &q) {
+        (void)hoff;
+        *reinterpret_cast<float4 *>(p + (cb << 4)) = make_float4(q.a, q.b, q.c, q.d);
     }
 };
 
 template <> struct Links<double> {
-    static __device__ __forceinline__ Q<double> ld(const void *base, long long blk, int vh, int cb) {
-        const double2 *p = reinterpret_cast<const double2 *>(base) + 2 * blk;
-        double2 lo = p[cb], hi = p[vh + cb];
-        return Q<double>{lo.x, lo.y, hi.x, hi.y};
+    static constexpr int BYTES = 32;
+    static __device__ __forceinline__ Q<double> ld(const char *p, uint32_t hoff, uint32_t cb) {
+        const uint32_t o = cb << 4;
+        const double2 l = *reinterpret_cast<const double2 *>(p + o);
+        const double2 h = *reinterpret_cast<const double2 *>(p + (o + hoff));
+        return Q<double>{l.x, l.y, h.x, h.y};
     }
-    static __device__ __forceinline__ void st(void *base, long long blk, int vh, int cb,
-                                              const Q<double> &q) {
-        double2 *p = reinterpret_cast<double2 *>(base) + 2 * blk;
-        p[cb] = make_double2(q.a, q.b);
-        p[vh + cb] = make_double2(q.c, q.d);
+    static __device__ __forceinline__ void st(char *p, uint32_t hoff, uint32_t cb, const Q<double> &q) {
+        const uint32_t o = cb << 4;
+        *reinterpret_cast<double2 *>(p + o) = make_double2(q.a, q.b);
+        *reinterpret_cast<double2 *>(p + (o + hoff)) = make_double2(q.c, q.d);
     }
 };
 
@@ -166,9 +186,10 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 template <class T> struct Mth;
 
 template <> struct Mth<float> {
-    // (2m+1) 2^-24, m = the top 23 bits: exact, in (0,1)
+    // (2m+1) 2^-24, m = the top 23 bits: exact, in (0,1).  Formed as
+    // (1 + m 2^-23) - (1 - 2^-24), an exact (Sterbenz) difference.
     static __device__ __forceinline__ float u(uint32_t w) {
-        return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f;
+        return __uint_as_float((w >> 9) | 0x3F800000u) - 0x1.fffffep-1f;
     }
     static __device__ __forceinline__ float ln(float x) {
         return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
@@ -183,9 +204,8 @@ template <> struct Mth<float> {
 };
 
 template <> struct Mth<double> {
-    static __device__ __forceinline__ double u(uint32_t w) {
-        return ((double)w * 2.0 + 1.0) * 0x1p-33;
-    }
+    // (2w+1) 2^-33 = w 2^-32 + 2^-33, exact
+    static __device__ __forceinline__ double u(uint32_t w) { return fma((double)w, 0x1p-32, 0x1p-33); }
     static __device__ __forceinline__ double ln(double x) { return log(x); }
     static __device__ __forceinline__ double cos2pi(double r) {
         return cos(6.283185307179586476925286766559 * r);
@@ -246,6 +266,29 @@ __device__ __forceinline__ void dd_block_sum(DD (&v)[K], DD *lds) {
 }
 
 // ---------------------------------------------------------------------------
+// Values every lane of a wavefront agrees on, moved to scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned uni(unsigned v) {
+    return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Descriptor of one lattice in scalar registers.
+__device__ __forceinline__ LatDesc load_desc(const LatDesc *p) {
+    static_assert(sizeof(LatDesc) % 4 == 0, "descriptor is a whole number of dwords");
+    LatDesc d;
+    const int *src = reinterpret_cast<const int *>(p);
+    int *dst = reinterpret_cast<int *>(&d);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(LatDesc) / 4); ++i) dst[i] = uni(src[i]);
+    return d;
+}
+
+__device__ __forceinline__ Tile load_tile(const Tile *t, int i) {
+    const Tile v = t[i];
+    return make_int2(uni(v.x), uni(v.y));
+}
+
+// ---------------------------------------------------------------------------
 // Tile walk of a persistent grid.  With xcd_remap, workgroup b runs on XCD
 // b % 8 (round-robin dispatch) and is given tiles from that XCD's
 // contiguous eighth of the tile list, so neighbouring tiles (which share
@@ -253,17 +296,15 @@ __device__ __forceinline__ void dd_block_sum(DD (&v)[K], DD *lds) {
 template <class F>
 __device__ __forceinline__ void for_each_tile(int ntiles, int xcd_remap, F &&body) {
     const int G = gridDim.x, b = blockIdx.x;
+    int base = 0, i = b, step = G, lim = ntiles;
     if (xcd_remap && (G & 7) == 0) {
-        const int x = b & 7, j = b >> 3, gx = G >> 3;
-        const int tx = (ntiles + 7) >> 3;
-        for (int i = j; i < tx; i += gx) {
-            const int t = x * tx + i;
-            if (t >= ntiles) break;
-            body(t);
-        }
-    } else {
-        for (int t = b; t < ntiles; t += G) body(t);
+        const int tx = (ntiles + 7) >> 3;  // tiles per XCD
+        base = (b & 7) * tx;
+        i = b >> 3;
+        step = G >> 3;
+        lim = min(tx, ntiles - base);
     }
+    for (; i < lim; i += step) body(base + i);
 }
 
 }  // namespace su2

@@ -13,14 +13,16 @@ struct KArgs {
     int ntiles;
     int xcd_remap;
     void *links;                         // native link buffer
-    DevState *st;                        // seed / sweep counter / error flag
+    const DevState *st;                  // seed / sweep counter
+    unsigned int *err;                   // sampler try-cap hits (&st->err)
     uint32_t *trace;                     // per-link try record or null
     unsigned long long *tries_part;      // per-tile try counts
+    double *plaq_part;                   // per-tile plaquette sums of the sweep
     int sampler;                         // 0 hybrid, 1 Creutz
 };
 
-void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s,
-                     bool trace);
+void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
+                     bool trace, bool plaq);
 void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s);
 void launch_init(const KArgs &a, bool f32, int hot, int block, int grid, hipStream_t s);
 void launch_from_canon(const KArgs &a, bool f32, const double *canon, int block, hipStream_t s);
@@ -29,8 +31,11 @@ void launch_to_canon(const KArgs &a, bool f32, const void *src, int ndir, double
 void launch_unit_defect(const KArgs &a, bool f32, unsigned long long *out, int block, hipStream_t s);
 void launch_plaquette(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
 void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
-void launch_finalize(const LatDesc *desc, int nlat, const double *part, int kind, const DevState *st,
-                     int series, double *out, long long ostride, hipStream_t s);
+// pp: plaquette partials of k_plaquette (4 per tile) or, with pp_hb, of
+// the heat-bath substeps (6 per heat-bath tile); pl: Polyakov partials.
+void launch_finalize(const LatDesc *desc, int nlat, const double *pp, int pp_hb, const double *pl,
+                     DevState *st, int series, int bump, double *outp, double *outl, long long ostride,
+                     hipStream_t s);
 void launch_bump(DevState *st, hipStream_t s);
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s);

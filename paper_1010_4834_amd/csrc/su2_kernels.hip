@@ -3,10 +3,11 @@
 // Method: Cardoso & Bicudo, "SU(2) Lattice Gauge Theory Simulations on Fermi
 // GPUs" (arXiv:1010.4834); each kernel names the passage it implements.
 // All kernels walk a (lattice, tile) list so one launch advances a whole
-// batch of independent lattices; the per-lattice descriptor is read with
-// scalar loads.  Nothing here is a dense contraction (at most 4x4 real
-// products per quaternion), so the kernels are vector-ALU code bound by HBM
-// traffic: coalesced float4 / float64x2 loads of the parity-split layout.
+// batch of independent lattices; per-tile lattice data live in scalar
+// registers and every link load is one global load from a scalar block base
+// plus a 32-bit lane offset.  Nothing here is a dense contraction (at most
+// 4x4 real products per quaternion): no MFMA, vector-ALU code fed by
+// coalesced float4 / float64x2 loads of the parity-split layout.
 #include "su2_internal.hpp"
 
 namespace su2 {
@@ -43,8 +44,45 @@ __device__ __forceinline__ int step_bwd(const LatDesc &d, const Site &S, int mu)
     return S.c[mu] == 0 ? (d.n[mu] - 1) * st : -st;
 }
 
-__device__ __forceinline__ long long blk(const LatDesc &d, int mu, int par) {
-    return d.off + (long long)(2 * mu + par) * d.vh;
+// Uniform bases of the (direction, parity) blocks of one lattice in a link
+// buffer whose lattice starts at link `first` ([mu][parity][cb]).
+template <class T, int NDIR> struct Blocks {
+    char *b[NDIR][2];
+    uint32_t hoff;
+};
+template <class T, int NDIR>
+__device__ __forceinline__ Blocks<T, NDIR> blocks(const void *buf, long long first, int vh) {
+    Blocks<T, NDIR> B;
+#pragma unroll
+    for (int mu = 0; mu < NDIR; ++mu)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+            B.b[mu][p] = (char *)buf + (first + (long long)(2 * mu + p) * vh) * Links<T>::BYTES;
+    B.hoff = (uint32_t)vh << 4;
+    return B;
+}
+
+// Block base of (mu, p); an unrolled select so the bases stay in scalar
+// registers (indexing the array with run-time values would spill it to
+// private memory and turn every link load into a flat load).
+template <class T, int NDIR>
+__device__ __forceinline__ char *bsel(const Blocks<T, NDIR> &B, int mu, int p) {
+    char *r = B.b[0][0];
+#pragma unroll
+    for (int m = 0; m < NDIR; ++m) {
+        r = (mu == m && p == 0) ? B.b[m][0] : r;
+        r = (mu == m && p == 1) ? B.b[m][1] : r;
+    }
+    return r;
+}
+
+template <class T, int NDIR>
+__device__ __forceinline__ Q<T> lds_(const Blocks<T, NDIR> &B, int mu, int p, uint32_t cb) {
+    return Links<T>::ld(bsel(B, mu, p), B.hoff, cb);
+}
+template <class T, int NDIR>
+__device__ __forceinline__ void sts_(const Blocks<T, NDIR> &B, int mu, int p, uint32_t cb, const Q<T> &q) {
+    Links<T>::st(bsel(B, mu, p), B.hoff, cb, q);
 }
 
 // Staple V of link (x, MU), x of parity `par` (paper Sec. 2: the six
@@ -55,8 +93,8 @@ __device__ __forceinline__ long long blk(const LatDesc &d, int mu, int par) {
 //   lower U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu).
 // 18 link loads; 7 distinct per update once shared with neighbouring lanes.
 template <class T, int MU>
-__device__ __forceinline__ Q<T> staple(const LatDesc &d, const void *L, const Site &S, int par) {
-    using IO = Links<T>;
+__device__ __forceinline__ Q<T> staple(const LatDesc &d, const Blocks<T, 4> &B, const Site &S, int par,
+                                       Q<T> (*Vlow)[3] = nullptr) {
     const int op = par ^ 1;
     const int s_mu = S.s + step_fwd(d, S, MU);
     Q<T> V{T(0), T(0), T(0), T(0)};
@@ -64,104 +102,194 @@ __device__ __forceinline__ Q<T> staple(const LatDesc &d, const void *L, const Si
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == MU) continue;
         const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
-        const Q<T> A = IO::ld(L, blk(d, nu, op), d.vh, s_mu >> 1);
-        const Q<T> B = IO::ld(L, blk(d, MU, op), d.vh, (S.s + fn) >> 1);
-        const Q<T> C = IO::ld(L, blk(d, nu, par), d.vh, S.s >> 1);
-        const Q<T> D = IO::ld(L, blk(d, nu, par), d.vh, (s_mu + bn) >> 1);
-        const Q<T> E = IO::ld(L, blk(d, MU, op), d.vh, (S.s + bn) >> 1);
-        const Q<T> F = IO::ld(L, blk(d, nu, op), d.vh, (S.s + bn) >> 1);
-        qacc(V, qmul(A, qdag(qmul(C, B))));
-        qacc(V, qmul(qdag(qmul(E, D)), F));
+        const Q<T> A = lds_(B, nu, op, (uint32_t)s_mu >> 1);
+        const Q<T> Bm = lds_(B, MU, op, (uint32_t)(S.s + fn) >> 1);
+        const Q<T> C = lds_(B, nu, par, (uint32_t)S.s >> 1);
+        const Q<T> D = lds_(B, nu, par, (uint32_t)(s_mu + bn) >> 1);
+        const Q<T> E = lds_(B, MU, op, (uint32_t)(S.s + bn) >> 1);
+        const Q<T> F = lds_(B, nu, op, (uint32_t)(S.s + bn) >> 1);
+        if (Vlow && nu < MU) {
+            // staple of plane (nu, MU) kept apart for the fused plaquette
+            Q<T> P{T(0), T(0), T(0), T(0)};
+            qmul_acc(P, A, qdag(qmul(C, Bm)));
+            qmul_acc(P, qdag(qmul(E, D)), F);
+            (*Vlow)[nu] = P;
+            qacc(V, P);
+        } else {
+            qmul_acc(V, A, qdag(qmul(C, Bm)));
+            qmul_acc(V, qdag(qmul(E, D)), F);
+        }
     }
     return V;
+}
+
+template <class T, int N> __device__ __forceinline__ T pick(const T (&a)[N], int m) {
+    T r = a[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) r = (m == k) ? a[k] : r;
+    return r;
+}
+template <class T, int N> __device__ __forceinline__ void put(T (&a)[N], int m, T v) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (m == k) a[k] = v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+    return t;
 }
 
 // ---------------------------------------------------------------------------
 // Heat-bath substep (paper Sec. 2 heat bath; Sec. 4 chessboard): every link
 // (x, MU) with parity(x) = par is redrawn from exp(beta/2 Tr(U V)).
-// delta = 1 - a0 from Kennedy-Pendleton (alpha >= 2) or Creutz (alpha < 2,
-// or always with SU2_CREUTZ); one Philox call per try, counter (s, sweep,
-// tag, try).  Direction from the call with try word 0xFFFFFFFF.  New link
-// X W^dag with W = V/k, renormalised in binary64.
-template <class T, int MU, bool TRACE>
+// a0 from Kennedy-Pendleton (alpha >= 2) or Creutz (alpha < 2, or always
+// with the Creutz sampler); one Philox call per try, counter (s, sweep,
+// tag, try); the direction of the vector part from the call with try word
+// 0xFFFFFFFF.  New link X W^dag with W = V/k, renormalised with a binary64
+// norm.
+//
+// Each lane owns NL links of the class (one per block-sized slice of its
+// tile).  Staples first; then a single rejection loop in which a lane moves
+// on to its next link as soon as one is accepted, so a wavefront waits for
+// the lane with the most tries over NL links rather than NL times for the
+// slowest lane; then the new links are composed and stored.
+//
+// PLAQ (odd substeps, MU >= 1): every plaquette of a plane (nu, MU) with
+// nu < MU holds exactly one MU-link at an odd site, updated here after all
+// its other links are final; 1/2 Tr(U' (upper + lower staple of plane nu))
+// over nu < MU and over the three odd substeps MU = 1, 2, 3 is therefore the
+// plaquette sum (paper Sec. 2, eq. for <P>) of the configuration at the end
+// of the sweep.  Slot MU-1 of the tile's six partials holds it.
+template <class T, int MU, bool TRACE, int NL, bool PLAQ>
 __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
     using M = Mth<T>;
+    const uint32_t sweep = uni(a.st->sweep);
+    const uint32_t k0 = uni((unsigned)a.st->seed), k1 = uni((unsigned)(a.st->seed >> 32));
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
-        const int cb = tl.y + (int)threadIdx.x;
-        uint32_t tries = 0;
-        if (cb < d.vh) {
-            const Site S = site_of(d, cb, par);
-            const Q<T> V = staple<T, MU>(d, a.links, S, par);
-            const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
-            const T beta = (sizeof(T) == 4) ? (T)d.betaf : (T)d.beta;
-            T k, ik;
-            if (sizeof(T) == 4) {
-                ik = M::rsqrt_(k2);
-                k = k2 > T(0) ? k2 * ik : T(0);
-            } else {
-                k = M::sqrt_(k2);
-                ik = T(1) / k;
-            }
-            const T alpha = beta * k;
-            const uint32_t c0 = (uint32_t)S.s, c1 = a.st->sweep, c2 = tag(d.lat_id, PURPOSE_HEATBATH, MU, par);
-            const unsigned long long seed = a.st->seed;
-            const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-            const bool creutz = (a.sampler == 1) || !(alpha >= T(2));
-            const T cfac = creutz ? -M::expm1_(T(-2) * alpha) : T(0);
-            const T hia = T(0.5) / alpha;
-            const T ia = T(1) / alpha;
-            T delta = T(0);
-            bool done = false;
-            for (uint32_t j = 0; j < MAX_TRIES; ++j) {
-                const uint4 w = philox10(c0, c1, c2, j, k0, k1);
-                bool acc;
-                T dl;
-                if (creutz) {
-                    const T u1 = M::u(w.x), u2 = M::u(w.y);
-                    dl = (alpha >= T(1e-20)) ? -M::log1p_(-(T(1) - u1) * cfac) * ia
-                                             : T(2) * (T(1) - u1);
-                    acc = u2 * u2 <= dl * (T(2) - dl);
-                } else {
-                    const T r1 = M::u(w.x), r2 = M::u(w.y), r3 = M::u(w.z), r4 = M::u(w.w);
-                    const T cs = M::cos2pi(r2);
-                    const T lam2 = -(M::ln(r1) + cs * cs * M::ln(r3)) * hia;
-                    acc = r4 * r4 <= T(1) - lam2;
-                    dl = T(2) * lam2;
-                }
-                if (acc) {
-                    delta = dl;
-                    tries = j + 1;
-                    done = true;
-                    break;
-                }
-            }
-            if (!done) {
-                atomicAdd(&a.st->err, 1u);
-                delta = M::nan_();
-                tries = MAX_TRIES;
-            }
-            const uint4 w = philox10(c0, c1, c2, 0xFFFFFFFFu, k0, k1);
-            const T u1 = M::u(w.x), u2 = M::u(w.y);
-            const T cth = T(1) - T(2) * u1;
-            const T sth = T(2) * M::sqrt_(u1 * (T(1) - u1));
-            const T ra = M::sqrt_(delta * (T(2) - delta));
-            const T rs = ra * sth;
-            const Q<T> X{T(1) - delta, rs * M::cos2pi(u2), rs * M::sin2pi(u2), ra * cth};
-            Q<T> Wd;
-            if (k2 > T(0)) Wd = Q<T>{V.a * ik, -V.b * ik, -V.c * ik, -V.d * ik};
-            else Wd = qone<T>();
-            const Q<T> Un = qnormalize(qmul(X, Wd));
-            Links<T>::st(a.links, blk(d, MU, par), d.vh, cb, Un);
-            if (TRACE)
-                a.trace[d.toff + (long long)S.s * 4 + MU] = tries | ((uint32_t)creutz << 31);
-        }
-        // tries of this tile: one atomic per wavefront, spread over tiles
-        uint32_t t = tries;
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
+        const uint32_t c2 = tag(d.lat_id, PURPOSE_HEATBATH, MU, par);
+        const T beta = (sizeof(T) == 4) ? (T)d.betaf : (T)d.beta;
+
+        int sidx[NL];
+        T alpha[NL];
+        Q<T> Wd[NL];
+        Q<T> Vl[NL][3];  // per-plane staples nu < MU (PLAQ only)
+        uint32_t pend = 0;
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
-        if ((threadIdx.x & 63) == 0 && t) atomicAdd(&a.tries_part[tile], (unsigned long long)t);
+        for (int m = 0; m < NL; ++m) {
+            const int cb = tl.y + m * (int)blockDim.x + (int)threadIdx.x;
+            sidx[m] = 0;
+            alpha[m] = T(0);
+            Wd[m] = qone<T>();
+            if (cb < d.vh) {
+                pend |= 1u << m;
+                const Site S = site_of(d, cb, par);
+                const Q<T> V = staple<T, MU>(d, B, S, par, PLAQ ? &Vl[m] : nullptr);
+                const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
+                T k, ik;
+                if (sizeof(T) == 4) {
+                    ik = M::rsqrt_(k2);
+                    k = k2 > T(0) ? k2 * ik : T(0);
+                } else {
+                    k = M::sqrt_(k2);
+                    ik = T(1) / k;
+                }
+                sidx[m] = S.s;
+                alpha[m] = beta * k;
+                if (k2 > T(0)) Wd[m] = Q<T>{V.a * ik, -V.b * ik, -V.c * ik, -V.d * ik};
+            }
+        }
+
+        // Rejection loop: a lane moves to its next link when one is accepted.
+        T delta[NL];
+        uint32_t rec[NL];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            delta[m] = T(0);
+            rec[m] = 0;
+        }
+        uint32_t j = 0;
+        while (pend) {
+            const int m = __builtin_ctz(pend);
+            const int s = pick(sidx, m);
+            const T al = pick(alpha, m);
+            const bool creutz = (a.sampler == 1) || !(al >= T(2));
+            const uint4 w = philox10((uint32_t)s, sweep, c2, j, k0, k1);
+            bool acc;
+            T dl;
+            if (creutz) {
+                const T u1 = M::u(w.x), u2 = M::u(w.y);
+                if (al >= T(1e-20)) {
+                    const T cf = -M::expm1_(T(-2) * al);
+                    dl = -M::log1p_(-(T(1) - u1) * cf) / al;
+                } else {
+                    dl = T(2) * (T(1) - u1);
+                }
+                acc = u2 * u2 <= dl * (T(2) - dl);
+            } else {
+                const T r1 = M::u(w.x), r2 = M::u(w.y), r3 = M::u(w.z), r4 = M::u(w.w);
+                const T cs = M::cos2pi(r2);
+                const T lam2 = -(M::ln(r1) + cs * cs * M::ln(r3)) / (T(2) * al);
+                acc = r4 * r4 <= T(1) - lam2;
+                dl = T(2) * lam2;
+            }
+            ++j;
+            if (acc || j >= MAX_TRIES) {
+                if (!acc) {
+                    atomicAdd(a.err, 1u);
+                    dl = M::nan_();
+                }
+                put(delta, m, dl);
+                put(rec, m, j | ((uint32_t)creutz << 31));
+                pend &= pend - 1;
+                j = 0;
+            }
+        }
+
+        // Direction from its own Philox call (try word 0xFFFFFFFF), then
+        // U' = X W^dag, renormalised.
+        uint32_t tries = 0;
+        double pq = 0.0;
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int cb = tl.y + m * (int)blockDim.x + (int)threadIdx.x;
+            if (cb < d.vh) {
+                const uint4 w = philox10((uint32_t)sidx[m], sweep, c2, 0xFFFFFFFFu, k0, k1);
+                const T u1 = M::u(w.x), u2 = M::u(w.y);
+                const T dl = delta[m];
+                const T cth = T(1) - T(2) * u1;
+                const T sth = T(2) * M::sqrt_(u1 * (T(1) - u1));
+                const T ra = M::sqrt_(dl * (T(2) - dl));
+                const T rs = ra * sth;
+                const Q<T> X{T(1) - dl, rs * M::cos2pi(u2), rs * M::sin2pi(u2), ra * cth};
+                const Q<T> Un = qnormalize(qmul(X, Wd[m]));
+                sts_(B, MU, par, (uint32_t)cb, Un);
+                if (TRACE) a.trace[d.toff + (long long)sidx[m] * 4 + MU] = rec[m];
+                tries += rec[m] & 0x7FFFFFFFu;
+                if (PLAQ) {
+#pragma unroll
+                    for (int nu = 0; nu < MU; ++nu) {  // 1/2 Re Tr(U' V_nu)
+                        const Q<T> &P = Vl[m][nu];
+                        pq += (double)(Un.a * P.a - Un.b * P.b - Un.c * P.c - Un.d * P.d);
+                    }
+                }
+            }
+        }
+        if (PLAQ) {
+            __shared__ DD lds[4];
+            DD acc[1] = {{pq, 0.0}};
+            dd_block_sum<1>(acc, lds);
+            if (threadIdx.x == 0) {
+                a.plaq_part[6 * tile + 2 * (MU - 1)] = acc[0].hi;
+                a.plaq_part[6 * tile + 2 * (MU - 1) + 1] = acc[0].lo;
+            }
+        }
+        tries = wave_sum_u32(tries);
+        if ((threadIdx.x & 63) == 0 && tries) atomicAdd(&a.tries_part[tile], (unsigned long long)tries);
     });
 }
 
@@ -170,19 +298,19 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
 template <class T, int MU>
 __global__ __launch_bounds__(256) void k_overrelax(KArgs a, int par) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
         const Site S = site_of(d, cb, par);
-        const Q<T> V = staple<T, MU>(d, a.links, S, par);
+        const Q<T> V = staple<T, MU>(d, B, S, par);
         const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
         if (!(k2 > T(0))) return;
         const T ik = T(1) / Mth<T>::sqrt_(k2);
         const Q<T> Wd{V.a * ik, -V.b * ik, -V.c * ik, -V.d * ik};
-        const Q<T> U = Links<T>::ld(a.links, blk(d, MU, par), d.vh, cb);
-        const Q<T> Un = qnormalize(qmul(qmul(Wd, qdag(U)), Wd));
-        Links<T>::st(a.links, blk(d, MU, par), d.vh, cb, Un);
+        const Q<T> U = lds_(B, MU, par, (uint32_t)cb);
+        sts_(B, MU, par, (uint32_t)cb, qnormalize(qmul(qmul(Wd, qdag(U)), Wd)));
     });
 }
 
@@ -193,12 +321,13 @@ __global__ __launch_bounds__(256) void k_overrelax(KArgs a, int par) {
 // normalised, rounded to the link precision.
 template <class T>
 __global__ __launch_bounds__(256) void k_init(KArgs a, int hot) {
+    const unsigned long long seed = a.st->seed;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        const unsigned long long seed = a.st->seed;
         for (int par = 0; par < 2; ++par) {
             const Site S = site_of(d, cb, par);
             for (int mu = 0; mu < 4; ++mu) {
@@ -215,47 +344,47 @@ __global__ __launch_bounds__(256) void k_init(KArgs a, int hot) {
                     const double nrm = sqrt(z.a * z.a + z.b * z.b + z.c * z.c + z.d * z.d);
                     z = Q<double>{z.a / nrm, z.b / nrm, z.c / nrm, z.d / nrm};
                 }
-                Links<T>::st(a.links, blk(d, mu, par), d.vh, cb,
-                             Q<T>{(T)z.a, (T)z.b, (T)z.c, (T)z.d});
+                sts_(B, mu, par, (uint32_t)cb, Q<T>{(T)z.a, (T)z.b, (T)z.c, (T)z.d});
             }
         }
     });
 }
 
-// Canonical float64 [s][mu][4] <-> native layout.
+// Canonical float64 [s][mu][4] <-> native layout (ndir = 4: links,
+// ndir = 3: smeared spatial links).
 template <class T>
 __global__ __launch_bounds__(256) void k_from_canon(KArgs a, const double *canon) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        const double *c = canon + 16 * (d.off / 4);
+        const double *c = canon + 4 * d.off;
         for (int par = 0; par < 2; ++par) {
             const Site S = site_of(d, cb, par);
             for (int mu = 0; mu < 4; ++mu) {
                 const double *u = c + ((long long)S.s * 4 + mu) * 4;
-                Links<T>::st(a.links, blk(d, mu, par), d.vh, cb, Q<T>{(T)u[0], (T)u[1], (T)u[2], (T)u[3]});
+                sts_(B, mu, par, (uint32_t)cb, Q<T>{(T)u[0], (T)u[1], (T)u[2], (T)u[3]});
             }
         }
     });
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_to_canon(KArgs a, const void *src, long long src_stride_dirs,
-                                                   int ndir, double *canon) {
+__global__ __launch_bounds__(256) void k_to_canon(KArgs a, const void *src, int ndir, double *canon) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const long long base = ndir == 4 ? d.off : d.soff;
+        const Blocks<T, 4> B = blocks<T, 4>(src, base, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        const long long base = ndir == 4 ? d.off : d.soff;
-        double *c = canon + (long long)ndir * 4 * (base / ndir);
-        (void)src_stride_dirs;
+        double *c = canon + 4 * base;
         for (int par = 0; par < 2; ++par) {
             const Site S = site_of(d, cb, par);
             for (int mu = 0; mu < ndir; ++mu) {
-                const Q<T> q = Links<T>::ld(src, base + (long long)(2 * mu + par) * d.vh, d.vh, cb);
+                const Q<T> q = lds_(B, mu, par, (uint32_t)cb);
                 double *u = c + ((long long)S.s * ndir + mu) * 4;
                 u[0] = q.a; u[1] = q.b; u[2] = q.c; u[3] = q.d;
             }
@@ -267,13 +396,15 @@ __global__ __launch_bounds__(256) void k_to_canon(KArgs a, const void *src, long
 template <class T>
 __global__ __launch_bounds__(256) void k_unit_defect(KArgs a, unsigned long long *out) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         double m = 0.0;
         if (cb < d.vh)
+#pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const Q<T> u = Links<T>::ld(a.links, d.off + (long long)q * d.vh, d.vh, cb);
+                const Q<T> u = lds_(B, q >> 1, q & 1, (uint32_t)cb);
                 const double n2 = (double)u.a * u.a + (double)u.b * u.b + (double)u.c * u.c +
                                   (double)u.d * u.d;
                 const double e = fabs(1.0 - n2);
@@ -285,7 +416,7 @@ __global__ __launch_bounds__(256) void k_unit_defect(KArgs a, unsigned long long
             m = (o > m || o != o) ? o : m;
         }
         if ((threadIdx.x & 63) == 0) {
-            unsigned long long bits = (m != m) ? 0x7FF8000000000000ull : __double_as_longlong(m);
+            const unsigned long long bits = (m != m) ? 0x7FF8000000000000ull : __double_as_longlong(m);
             atomicMax(out, bits);
         }
     });
@@ -299,28 +430,30 @@ __global__ __launch_bounds__(256) void k_unit_defect(KArgs a, unsigned long long
 // per tile (spatial, temporal planes).
 template <class T>
 __global__ __launch_bounds__(256) void k_plaquette(KArgs a, double *part) {
-    __shared__ DD lds[2 * 16];
+    __shared__ DD lds[2 * 4];
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         DD acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
         if (cb < d.vh) {
             double sp = 0.0, tp = 0.0;
+#pragma unroll
             for (int par = 0; par < 2; ++par) {
                 const Site S = site_of(d, cb, par);
                 const int op = par ^ 1;
                 Q<T> U[4];
 #pragma unroll
-                for (int mu = 0; mu < 4; ++mu) U[mu] = Links<T>::ld(a.links, blk(d, mu, par), d.vh, cb);
+                for (int mu = 0; mu < 4; ++mu) U[mu] = lds_(B, mu, par, (uint32_t)cb);
 #pragma unroll
                 for (int mu = 0; mu < 4; ++mu) {
-                    const int smu = (S.s + step_fwd(d, S, mu)) >> 1;
+                    const uint32_t smu = (uint32_t)(S.s + step_fwd(d, S, mu)) >> 1;
 #pragma unroll
                     for (int nu = mu + 1; nu < 4; ++nu) {
-                        const int snu = (S.s + step_fwd(d, S, nu)) >> 1;
-                        const Q<T> Unu_smu = Links<T>::ld(a.links, blk(d, nu, op), d.vh, smu);
-                        const Q<T> Umu_snu = Links<T>::ld(a.links, blk(d, mu, op), d.vh, snu);
+                        const uint32_t snu = (uint32_t)(S.s + step_fwd(d, S, nu)) >> 1;
+                        const Q<T> Unu_smu = lds_(B, nu, op, smu);
+                        const Q<T> Umu_snu = lds_(B, mu, op, snu);
                         const T tr = half_tr_xyd(qmul(U[mu], Unu_smu), qmul(U[nu], Umu_snu));
                         if (nu == 3) tp += (double)tr;
                         else sp += (double)tr;
@@ -342,10 +475,11 @@ __global__ __launch_bounds__(256) void k_plaquette(KArgs a, double *part) {
 // of the temporal links t = 0 .. Nt-1 in ascending t, half trace.
 template <class T>
 __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
-    __shared__ DD lds[16];
+    __shared__ DD lds[4];
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int xs = tl.y + (int)threadIdx.x;
         DD acc[1] = {{0.0, 0.0}};
         if (xs < d.ns) {
@@ -353,10 +487,10 @@ __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
             udiv(xs, d.n[0], d.inv_nx, row, x);
             udiv(row, d.n[1], d.inv_ny, z, y);
             Q<T> P = qone<T>();
+            const int p0 = (x + y + z) & 1;
             for (int t = 0; t < d.n[3]; ++t) {
-                const int s = xs + d.ns * t;
-                const int par = (x + y + z + t) & 1;
-                P = qmul(P, Links<T>::ld(a.links, blk(d, 3, par), d.vh, s >> 1));
+                const uint32_t cb = (uint32_t)(xs + d.ns * t) >> 1;
+                P = qmul(P, lds_(B, 3, (p0 + t) & 1, cb));
             }
             acc[0] = DD{(double)P.a, 0.0};
         }
@@ -368,41 +502,62 @@ __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
     });
 }
 
-// Final per-lattice reduction of tile partials in a fixed order.
-// kind 0: plaquette (K = 2: spatial, temporal) -> (avg, spatial, temporal)
-// kind 1: Polyakov (K = 1) -> value / N_sigma
-// Output slot: out[l * ostride + idx * width], idx = sweep - run_base when
-// `series`, else 0.
-template <int K>
-__global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const double *part, int kind,
-                                                  const DevState *st, int series, double *out,
-                                                  long long ostride) {
-    __shared__ DD lds[K * 4];
-    const LatDesc &d = desc[blockIdx.x];
-    const int t0 = kind == 0 ? d.tile0 : d.stile0;
-    const int nt = kind == 0 ? d.ntile : d.nstile;
-    DD acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = DD{0.0, 0.0};
-    for (int t = threadIdx.x; t < nt; t += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            acc[k] = dd_add(acc[k], DD{part[2 * K * (t0 + t) + 2 * k], part[2 * K * (t0 + t) + 2 * k + 1]});
-    dd_block_sum<K>(acc, lds);
-    if (threadIdx.x == 0) {
-        const long long idx = series ? (long long)(st->sweep - st->run_base) : 0;
-        const double V = 2.0 * (double)d.vh;
-        if constexpr (K == 2) {
+// Final per-lattice reduction of tile partials in a fixed order; block l
+// handles lattice l.  Plaquette (avg, spatial, temporal) and/or Polyakov.
+// series: write slot (sweep - run_base) of out[l * ostride + slot] and, when
+// `bump`, the last block to arrive advances the sweep counter (every block
+// has read it before arriving).
+__global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const double *pp, int pp_hb,
+                                                  const double *pl, DevState *st, int series, int bump,
+                                                  double *outp, double *outl, long long ostride) {
+    __shared__ DD lds[2 * 4];
+    const LatDesc d = load_desc(desc + blockIdx.x);
+    const unsigned sweep = uni(st->sweep);
+    const long long idx = series ? (long long)(sweep - uni(st->run_base)) : 0;
+    const double V = 2.0 * (double)d.vh;
+    if (pp) {
+        DD acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+        if (pp_hb) {  // heat-bath partials: slots 0, 1 spatial planes, 2 temporal
+            for (int t = threadIdx.x; t < d.nmtile; t += blockDim.x) {
+                const double *q = pp + 6 * (long long)(d.mtile0 + t);
+                acc[0] = dd_add(dd_add(acc[0], DD{q[0], q[1]}), DD{q[2], q[3]});
+                acc[1] = dd_add(acc[1], DD{q[4], q[5]});
+            }
+        } else {
+            for (int t = threadIdx.x; t < d.ntile; t += blockDim.x) {
+                const double *q = pp + 4 * (long long)(d.tile0 + t);
+                acc[0] = dd_add(acc[0], DD{q[0], q[1]});
+                acc[1] = dd_add(acc[1], DD{q[2], q[3]});
+            }
+        }
+        dd_block_sum<2>(acc, lds);
+        if (threadIdx.x == 0) {
             const double sp = acc[0].hi + acc[0].lo, tp = acc[1].hi + acc[1].lo;
-            double *o = out + blockIdx.x * ostride + idx * (series ? 1 : 3);
-            o[0] = (sp + tp) / (6.0 * V);
-            if (!series) {
+            if (series) {
+                outp[blockIdx.x * ostride + idx] = (sp + tp) / (6.0 * V);
+            } else {
+                double *o = outp + blockIdx.x * ostride;
+                o[0] = (sp + tp) / (6.0 * V);
                 o[1] = sp / (3.0 * V);
                 o[2] = tp / (3.0 * V);
             }
-        } else {
-            double *o = out + blockIdx.x * ostride + idx;
-            o[0] = (acc[0].hi + acc[0].lo) / (double)d.ns;
+        }
+    }
+    if (pl) {
+        DD acc[1] = {{0.0, 0.0}};
+        for (int t = threadIdx.x; t < d.nstile; t += blockDim.x) {
+            const double *q = pl + 2 * (long long)(d.stile0 + t);
+            acc[0] = dd_add(acc[0], DD{q[0], q[1]});
+        }
+        dd_block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) outl[blockIdx.x * ostride + idx] = (acc[0].hi + acc[0].lo) / (double)d.ns;
+    }
+    if (bump && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned ticket = atomicAdd(&st->done, 1u);
+        if (ticket == gridDim.x - 1) {
+            st->done = 0u;
+            st->sweep = sweep + 1u;
         }
     }
 }
@@ -420,39 +575,40 @@ __global__ void k_bump(DevState *st) {
 // src_raw: read the lattice links (first step) or the smeared buffer.
 template <class T>
 __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_raw, void *dst, T alpha) {
-    using IO = Links<T>;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = a.tiles[tile];
-        const LatDesc &d = a.desc[tl.x];
+        const Tile tl = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tl.x);
+        const Blocks<T, 3> Bs = blocks<T, 3>(src, src_raw ? d.off : d.soff, d.vh);
+        const Blocks<T, 3> Bd = blocks<T, 3>(dst, d.soff, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        const long long sb = src_raw ? d.off : d.soff;
         for (int par = 0; par < 2; ++par) {
             const Site S = site_of(d, cb, par);
             const int op = par ^ 1;
+#pragma unroll
             for (int mu = 0; mu < 3; ++mu) {
                 const int s_mu = S.s + step_fwd(d, S, mu);
                 Q<T> sum{T(0), T(0), T(0), T(0)};
+#pragma unroll
                 for (int nu = 0; nu < 3; ++nu) {
                     if (nu == mu) continue;
                     const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
-                    const Q<T> a1 = IO::ld(src, sb + (2 * nu + par) * (long long)d.vh, d.vh, S.s >> 1);
-                    const Q<T> a2 = IO::ld(src, sb + (2 * mu + op) * (long long)d.vh, d.vh, (S.s + fn) >> 1);
-                    const Q<T> a3 = IO::ld(src, sb + (2 * nu + op) * (long long)d.vh, d.vh, s_mu >> 1);
+                    const Q<T> a1 = lds_(Bs, nu, par, (uint32_t)S.s >> 1);
+                    const Q<T> a2 = lds_(Bs, mu, op, (uint32_t)(S.s + fn) >> 1);
+                    const Q<T> a3 = lds_(Bs, nu, op, (uint32_t)s_mu >> 1);
                     qacc(sum, qmul(qmul(a1, a2), qdag(a3)));
-                    const Q<T> b1 = IO::ld(src, sb + (2 * nu + op) * (long long)d.vh, d.vh, (S.s + bn) >> 1);
-                    const Q<T> b2 = IO::ld(src, sb + (2 * mu + op) * (long long)d.vh, d.vh, (S.s + bn) >> 1);
-                    const Q<T> b3 = IO::ld(src, sb + (2 * nu + par) * (long long)d.vh, d.vh, (s_mu + bn) >> 1);
+                    const Q<T> b1 = lds_(Bs, nu, op, (uint32_t)(S.s + bn) >> 1);
+                    const Q<T> b2 = lds_(Bs, mu, op, (uint32_t)(S.s + bn) >> 1);
+                    const Q<T> b3 = lds_(Bs, nu, par, (uint32_t)(s_mu + bn) >> 1);
                     qacc(sum, qmul(qmul(qdag(b1), b2), b3));
                 }
-                const Q<T> u = IO::ld(src, sb + (2 * mu + par) * (long long)d.vh, d.vh, cb);
+                const Q<T> u = lds_(Bs, mu, par, (uint32_t)cb);
                 const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
                 const Q<T> w{w0 * u.a + w1 * sum.a, w0 * u.b + w1 * sum.b, w0 * u.c + w1 * sum.c,
                              w0 * u.d + w1 * sum.d};
                 const double n2 = (double)w.a * w.a + (double)w.b * w.b + (double)w.c * w.c +
                                   (double)w.d * w.d;
-                const Q<T> o = n2 > 0.0 ? qnormalize(w) : u;
-                IO::st(dst, d.soff + (2 * mu + par) * (long long)d.vh, d.vh, cb, o);
+                sts_(Bd, mu, par, (uint32_t)cb, n2 > 0.0 ? qnormalize(w) : u);
             }
         }
     });
@@ -465,11 +621,13 @@ __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_r
 //   tl[(T-1)*V + s], sl[(mu*Rmax + R-1)*V + s].
 // `sp` / `sp_raw`: the spatial links (smeared buffer or raw links).
 template <class T>
-__global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_raw, int Rmax,
-                                                 int Tmax, Q<T> *tl, Q<T> *sl) {
+__global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_raw, int Rmax, int Tmax,
+                                                Q<T> *tl, Q<T> *sl) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tv = a.tiles[tile];
-        const LatDesc &d = a.desc[tv.x];
+        const Tile tv = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tv.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
+        const Blocks<T, 3> Bs = blocks<T, 3>(sp, sp_raw ? d.off : d.soff, d.vh);
         const int s = tv.y + (int)threadIdx.x;
         const long long V = 2LL * d.vh;
         if (s >= V) return;
@@ -483,12 +641,12 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
             for (int TT = 1; TT <= Tmax; ++TT) {
                 const int y = s + (t - c[3]) * d.ns;
                 const int par = (c[0] + c[1] + c[2] + t) & 1;
-                P = qmul(P, Links<T>::ld(a.links, blk(d, 3, par), d.vh, y >> 1));
+                P = qmul(P, lds_(B, 3, par, (uint32_t)y >> 1));
                 tl[(long long)(TT - 1) * V + s] = P;
                 t = (t + 1 == d.n[3]) ? 0 : t + 1;
             }
         }
-        const long long sb = sp_raw ? d.off : d.soff;
+#pragma unroll
         for (int mu = 0; mu < 3; ++mu) {
             const int st = mu == 0 ? 1 : mu == 1 ? d.n[0] : d.n[0] * d.n[1];
             Q<T> P = qone<T>();
@@ -496,7 +654,7 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
             for (int R = 1; R <= Rmax; ++R) {
                 const int y = s + (cm - c[mu]) * st;
                 const int par = (c[0] + c[1] + c[2] + c[3] - c[mu] + cm) & 1;
-                P = qmul(P, Links<T>::ld(sp, sb + (2 * mu + par) * (long long)d.vh, d.vh, y >> 1));
+                P = qmul(P, lds_(Bs, mu, par, (uint32_t)y >> 1));
                 sl[((long long)mu * Rmax + R - 1) * V + s] = P;
                 cm = (cm + 1 == d.n[mu]) ? 0 : cm + 1;
             }
@@ -509,13 +667,13 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
 // = 1/2 Tr[(S(x;R) T(x+R mu;T)) (T(x;T) S(x+T t;R))^dag], summed over mu in
 // binary64 per lane, then a compensated block sum per (R, tile, T).
 template <class T, int TMAX>
-__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, const Q<T> *tl,
-                                                const Q<T> *sl, double *part) {
+__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, const Q<T> *tl, const Q<T> *sl,
+                                                double *part) {
     __shared__ DD lds[TMAX * 4];
     const int R = blockIdx.y + 1;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tv = a.tiles[tile];
-        const LatDesc &d = a.desc[tv.x];
+        const Tile tv = load_tile(a.tiles, tile);
+        const LatDesc d = load_desc(a.desc + tv.x);
         const int s = tv.y + (int)threadIdx.x;
         const long long V = 2LL * d.vh;
         DD acc[TMAX];
@@ -539,9 +697,8 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, con
 #pragma unroll
             for (int k = 0; k < TMAX; ++k) {
                 if (k < Tmax) {
-                    const int TT = k + 1;
-                    int ct = c[3] + TT;
-                    while (ct >= d.n[3]) ct -= d.n[3];
+                    int ct = c[3] + k + 1;
+                    if (ct >= d.n[3]) ct -= d.n[3];
                     const int sT = s + (ct - c[3]) * d.ns;
                     const Q<T> t0 = tl[(long long)k * V + s];
                     double v = 0.0;
@@ -557,17 +714,19 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, con
         }
         dd_block_sum<TMAX>(acc, lds);
         if (threadIdx.x == 0)
-            for (int k = 0; k < Tmax; ++k) {
-                double *p = part + 2 * (((long long)(R - 1) * a.ntiles + tile) * Tmax + k);
-                p[0] = acc[k].hi;
-                p[1] = acc[k].lo;
-            }
+#pragma unroll
+            for (int k = 0; k < TMAX; ++k)
+                if (k < Tmax) {
+                    double *p = part + 2 * (((long long)(R - 1) * a.ntiles + tile) * Tmax + k);
+                    p[0] = acc[k].hi;
+                    p[1] = acc[k].lo;
+                }
     });
 }
 
 // One block per (R, T): fixed-order sum over the tiles of lattice 0.
-__global__ __launch_bounds__(256) void k_wfinal(const LatDesc *desc, int ntiles, int Tmax,
-                                                const double *part, double *out) {
+__global__ __launch_bounds__(256) void k_wfinal(const LatDesc *desc, int ntiles, int Tmax, const double *part,
+                                                double *out) {
     __shared__ DD lds[4];
     const int R = blockIdx.x / Tmax + 1, k = blockIdx.x % Tmax;
     DD acc[1] = {{0.0, 0.0}};
@@ -587,26 +746,45 @@ static inline dim3 grid_of(const KArgs &a, int grid) {
     return dim3((unsigned)g);
 }
 
-template <class T, int MU>
-static void launch_hb_mu(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace) {
-    if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true>), grid_of(a, grid), dim3(block), 0, s, a, par);
-    else hipLaunchKernelGGL((k_heatbath<T, MU, false>), grid_of(a, grid), dim3(block), 0, s, a, par);
-}
-
-template <class T>
-static void launch_hb_t(const KArgs &a, int mu, int par, int block, int grid, hipStream_t s, bool trace) {
-    switch (mu) {
-    case 0: launch_hb_mu<T, 0>(a, par, block, grid, s, trace); break;
-    case 1: launch_hb_mu<T, 1>(a, par, block, grid, s, trace); break;
-    case 2: launch_hb_mu<T, 2>(a, par, block, grid, s, trace); break;
-    default: launch_hb_mu<T, 3>(a, par, block, grid, s, trace); break;
+template <class T, int MU, int NL>
+static void launch_hb_nl(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq) {
+    const dim3 g = grid_of(a, grid), b(block);
+    if (plaq) {
+        if constexpr (MU >= 1) {
+            if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, true>), g, b, 0, s, a, par);
+            else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, true>), g, b, 0, s, a, par);
+        }
+    } else {
+        if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, false>), g, b, 0, s, a, par);
+        else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, false>), g, b, 0, s, a, par);
     }
 }
 
-void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s,
-                     bool trace) {
-    if (f32) launch_hb_t<float>(a, mu, par, block, grid, s, trace);
-    else launch_hb_t<double>(a, mu, par, block, grid, s, trace);
+template <class T, int MU>
+static void launch_hb_mu(const KArgs &a, int par, int nl, int block, int grid, hipStream_t s, bool trace,
+                         bool plaq) {
+    switch (nl) {
+    case 1: launch_hb_nl<T, MU, 1>(a, par, block, grid, s, trace, plaq); break;
+    case 2: launch_hb_nl<T, MU, 2>(a, par, block, grid, s, trace, plaq); break;
+    default: launch_hb_nl<T, MU, 4>(a, par, block, grid, s, trace, plaq); break;
+    }
+}
+
+template <class T>
+static void launch_hb_t(const KArgs &a, int mu, int par, int nl, int block, int grid, hipStream_t s,
+                        bool trace, bool plaq) {
+    switch (mu) {
+    case 0: launch_hb_mu<T, 0>(a, par, nl, block, grid, s, trace, false); break;
+    case 1: launch_hb_mu<T, 1>(a, par, nl, block, grid, s, trace, plaq); break;
+    case 2: launch_hb_mu<T, 2>(a, par, nl, block, grid, s, trace, plaq); break;
+    default: launch_hb_mu<T, 3>(a, par, nl, block, grid, s, trace, plaq); break;
+    }
+}
+
+void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
+                     bool trace, bool plaq) {
+    if (f32) launch_hb_t<float>(a, mu, par, nl, block, grid, s, trace, plaq);
+    else launch_hb_t<double>(a, mu, par, nl, block, grid, s, trace, plaq);
 }
 
 template <class T>
@@ -636,8 +814,8 @@ void launch_from_canon(const KArgs &a, bool f32, const double *canon, int block,
 
 void launch_to_canon(const KArgs &a, bool f32, const void *src, int ndir, double *canon, int block,
                      hipStream_t s) {
-    if (f32) hipLaunchKernelGGL((k_to_canon<float>), grid_of(a, 0), dim3(block), 0, s, a, src, 0LL, ndir, canon);
-    else hipLaunchKernelGGL((k_to_canon<double>), grid_of(a, 0), dim3(block), 0, s, a, src, 0LL, ndir, canon);
+    if (f32) hipLaunchKernelGGL((k_to_canon<float>), grid_of(a, 0), dim3(block), 0, s, a, src, ndir, canon);
+    else hipLaunchKernelGGL((k_to_canon<double>), grid_of(a, 0), dim3(block), 0, s, a, src, ndir, canon);
 }
 
 void launch_unit_defect(const KArgs &a, bool f32, unsigned long long *out, int block, hipStream_t s) {
@@ -655,20 +833,21 @@ void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid
     else hipLaunchKernelGGL((k_polyakov<double>), grid_of(a, grid), dim3(block), 0, s, a, part);
 }
 
-void launch_finalize(const LatDesc *desc, int nlat, const double *part, int kind, const DevState *st,
-                     int series, double *out, long long ostride, hipStream_t s) {
-    if (kind == 0)
-        hipLaunchKernelGGL((k_finalize<2>), dim3(nlat), dim3(256), 0, s, desc, part, kind, st, series, out, ostride);
-    else
-        hipLaunchKernelGGL((k_finalize<1>), dim3(nlat), dim3(256), 0, s, desc, part, kind, st, series, out, ostride);
+void launch_finalize(const LatDesc *desc, int nlat, const double *pp, int pp_hb, const double *pl,
+                     DevState *st, int series, int bump, double *outp, double *outl, long long ostride,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(nlat), dim3(256), 0, s, desc, pp, pp_hb, pl, st, series, bump, outp,
+                       outl, ostride);
 }
 
 void launch_bump(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, st); }
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s) {
-    if (f32) hipLaunchKernelGGL((k_ape<float>), grid_of(a, grid), dim3(block), 0, s, a, src, src_raw, dst, (float)alpha);
-    else hipLaunchKernelGGL((k_ape<double>), grid_of(a, grid), dim3(block), 0, s, a, src, src_raw, dst, alpha);
+    if (f32)
+        hipLaunchKernelGGL((k_ape<float>), grid_of(a, grid), dim3(block), 0, s, a, src, src_raw, dst, (float)alpha);
+    else
+        hipLaunchKernelGGL((k_ape<double>), grid_of(a, grid), dim3(block), 0, s, a, src, src_raw, dst, alpha);
 }
 
 void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,

@@ -52,3 +52,21 @@ def test_ensemble_fp32_c5_shapes(su2, orc):
     assert worst < 1e-4
     assert np.isfinite(P).all() and np.isfinite(L).all()
     ens.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-13), ("F32", 2e-7)])
+def test_fused_plaquette_matches_standalone(su2, prec, tol):
+    """The plaquette series summed inside the odd heat-bath substeps equals
+    the standalone plaquette kernel on the configuration after each sweep."""
+    dims = [(8, 6, 4, 10), (6, 6, 6, 6)]
+    p = getattr(su2, prec)
+    ens = su2.Ensemble(dims, [2.4, 2.7], start=su2.HOT, seed=7, prec=p)
+    for launch in ((256, 0, 1, 1), (64, 16, 0, 2), (128, 0, 1, 4)):
+        su2.su2_ensemble_set_launch(ens.h, *launch)
+        P, _ = ens.run(1, 7, plaq=True, poly=False)
+        for i, d in enumerate(dims):
+            lat = su2.Lattice(d, start=su2.COLD, prec=p)
+            lat.set_links(ens.get_links(i))
+            assert abs(P[i, 0] - lat.plaquette()[0]) < tol, (launch, i)
+            lat.close()
+    ens.close()

@@ -177,15 +177,16 @@ def test_launch_shapes_bitwise(su2, orc):
     dims = (6, 4, 10, 6)
     U = inputs.random_config(dims, 35)
     ref = None
-    for block, grid, remap in ((256, 0, 1), (64, 0, 0), (128, 16, 1), (192, 8, 0), (64, 24, 1)):
+    for block, grid, remap, nl in ((256, 0, 1, 1), (64, 0, 0, 2), (128, 16, 1, 4), (192, 8, 0, 1),
+                                   (64, 24, 1, 4), (256, 0, 0, 2)):
         lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
-        su2.su2_set_launch(lat.h, block, grid, remap)
+        su2.su2_set_launch(lat.h, block, grid, remap, nl)
         lat.set_links(U)
         lat.heatbath(2.4, 3, 6)
         G = lat.get_links()
         if ref is None:
             ref = G
-        assert np.array_equal(G, ref), (block, grid, remap)
+        assert np.array_equal(G, ref), (block, grid, remap, nl)
         lat.close()
     os.environ["SU2_NO_GRAPH"] = "1"
     try:

@@ -89,6 +89,32 @@ def test_sampler_distribution(orc, alpha, sampler):
     assert abs(a0.mean() - mean) < 5 * a0.std() / np.sqrt(n)
 
 
+@pytest.mark.parametrize("alpha,sampler", [(0.5, "HYBRID"), (2.0, "HYBRID"), (3.0, "HYBRID"),
+                                           (12.0, "HYBRID"), (12.0, "CREUTZ")])
+def test_link_draw_direction(orc, alpha, sampler):
+    """X = (a0, a): |X| = 1, a0 from the closed-form law, and a/|a| uniform
+    on the sphere (cos theta and phi uniform) independently of a0."""
+    n = 30000
+    X = np.array([orc.sample_link(alpha, getattr(orc, sampler), 9, [i, 3, 5])[0]
+                  for i in range(n)])
+    assert np.abs(np.linalg.norm(X, axis=1) - 1).max() < 1e-14
+    assert chi2_delta(1 - X[:, 0], alpha) > 1e-4
+    y = X[:, 1:] / np.linalg.norm(X[:, 1:], axis=1, keepdims=True)
+    edges = np.linspace(-1, 1, 21)
+    for comp in range(3):       # each component of a uniform unit vector is uniform
+        h = np.histogram(y[:, comp], edges)[0]
+        assert stats.chisquare(h).pvalue > 1e-4, comp
+    phi = np.arctan2(y[:, 1], y[:, 0])
+    assert stats.chisquare(np.histogram(phi, np.linspace(-np.pi, np.pi, 21))[0]).pvalue > 1e-4
+    q = np.quantile(X[:, 0], [0, 0.25, 0.5, 0.75, 1])
+    for lo, hi in zip(q[:-1], q[1:]):
+        sel = (X[:, 0] >= lo) & (X[:, 0] <= hi)
+        for comp in range(3):
+            m = (y[sel, comp] ** 2).mean()
+            assert abs(m - 1 / 3) < 5 * np.sqrt(4 / 45 / sel.sum()), (lo, comp, m)
+        assert abs((y[sel, 0] * y[sel, 2]).mean()) < 5 * np.sqrt(1 / 15 / sel.sum())
+
+
 def test_sampler_fp32_uniforms(orc):
     d, _ = orc.sample_many(8.0, orc.HYBRID, 6, 100000, ubits=23)
     assert chi2_delta(d, 8.0) > 1e-4
