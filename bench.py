@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--launch", default=None,
+                    help="block,grid,xcd_remap,links_per_lane,waves (skips tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -94,9 +96,11 @@ def main():
 
     ens = su2.su2_ensemble_create(dims, betas, su2.HOT, seed, su2.F32)
     su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
-    if not args.no_tune:
+    if args.launch:
+        su2.su2_ensemble_set_launch(ens, *[int(x) for x in args.launch.split(",")])
+    elif not args.no_tune:
         su2.su2_ensemble_autotune(ens)
-    block, grid, remap, nl = su2.su2_ensemble_get_launch(ens)
+    block, grid, remap, nl, waves = su2.su2_ensemble_get_launch(ens)
     su2.su2_ensemble_run(ens, n, args.warmup, seed, True, cfg["poly"])
 
     # ---- timed region: K steps, graph replay, one D2H of the series ----
@@ -144,7 +148,7 @@ def main():
                    "links": "binary32, binary64 reductions and norm", "sweeps_per_step": 1,
                    "sampler": "Kennedy-Pendleton (alpha>=2) / Creutz",
                    "launch": {"block": block, "grid": grid, "xcd_remap": remap,
-                              "links_per_lane": nl}},
+                              "links_per_lane": nl, "waves_per_simd": waves}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_heatbath<float> (one checkerboard substep)",

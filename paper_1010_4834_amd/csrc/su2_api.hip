@@ -48,7 +48,7 @@ struct su2_ensemble_s {
     long long total_links = 0;  // 4 * sum V
     long long total_sites = 0;
 
-    int block = 256, grid = 0, remap = 1, nl = 1;
+    int block = 256, grid = 0, remap = 1, nl = 1, waves = 0;
     std::vector<Tile> htiles, hstiles, hvtiles, hmtiles;
     Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr, *mtiles = nullptr;
     int ntiles = 0, nstiles = 0, nvtiles = 0, nmtiles = 0;
@@ -64,6 +64,9 @@ struct su2_ensemble_s {
     unsigned long long updates = 0;
 
     double *part_plaq = nullptr, *part_poly = nullptr, *part_hb = nullptr;
+    unsigned *fin_cnt = nullptr;    // per-lattice arrival tickets of the final reduction
+    double *fin_chunk = nullptr;    // per-workgroup chunk sums of the final reduction
+    int fin_chunks = 1;             // workgroups per lattice in the final reduction
     double *res = nullptr;   // device scratch for single results
     double *hres = nullptr;  // pinned host mirror of res
     double *ser_plaq = nullptr, *ser_poly = nullptr;
@@ -269,7 +272,16 @@ su2_status build_tiles(su2_ensemble_s *E) {
     CHK(dalloc(E, &E->tries_part, sizeof(unsigned long long) * E->ntiles));
     CHK(dalloc(E, &E->part_plaq, sizeof(double) * 4 * E->ntiles));
     CHK(dalloc(E, &E->part_poly, sizeof(double) * 2 * E->nstiles));
-    CHK(dalloc(E, &E->part_hb, sizeof(double) * 6 * E->nmtiles));
+    CHK(dalloc(E, &E->part_hb, sizeof(double) * 12 * E->nmtiles));
+    {   // final-reduction workgroups per lattice: ~2048 partial tiles each
+        int most = 1;
+        for (const LatDesc &d : E->hdesc) most = std::max(most, std::max(d.nmtile, std::max(d.ntile, d.nstile)));
+        E->fin_chunks = std::min(64, std::max(1, (most + 2047) / 2048));
+    }
+    CHK(dalloc(E, &E->fin_cnt, sizeof(unsigned) * E->n));
+    CHK(dalloc(E, &E->fin_chunk, sizeof(double) * 6 * (size_t)E->n * E->fin_chunks));
+    HIPCHK(hipMemsetAsync(E->fin_cnt, 0, sizeof(unsigned) * E->n, E->stream()));
+    HIPCHK(hipMemsetAsync(E->part_hb, 0, sizeof(double) * 12 * E->nmtiles, E->stream()));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, E->stream()));
     HIPCHK(hipMemcpyAsync(E->tiles, E->htiles.data(), sizeof(Tile) * E->ntiles, hipMemcpyHostToDevice,
                           E->stream()));
@@ -379,7 +391,7 @@ void destroy_common(su2_ensemble_s *E) {
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
     void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->st, E->tries_part, E->part_plaq,
-                    E->part_poly, E->part_hb, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1], E->wl_t,
+                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1], E->wl_t,
                     E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -397,7 +409,8 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
             Timed t(E, SU2_K_HEATBATH, s);
-            su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq);
+            su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq,
+                                 E->waves);
             t.done(s);
         }
     if (meas & 2) {
@@ -408,9 +421,9 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
     if (meas) {
         // per-lattice series values; the last block advances the sweep counter
         Timed r(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, (meas & 1) ? E->part_hb : nullptr, 1,
-                             (meas & 2) ? E->part_poly : nullptr, E->st, 1, 1, E->ser_plaq, E->ser_poly,
-                             E->ser_cap, s);
+        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, (meas & 1) ? E->part_hb : nullptr, 1,
+                             (meas & 2) ? E->part_poly : nullptr, E->st, E->fin_cnt, E->fin_chunk, 1, 1,
+                             E->ser_plaq, E->ser_poly, E->ser_cap, s);
         r.done(s);
     } else {
         su2::launch_bump(E->st, s);
@@ -475,7 +488,8 @@ su2_status measure_plaquette(su2_ensemble_s *E, int l, double *avg, double *sp, 
     }
     {
         Timed t(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->part_plaq, 0, nullptr, E->st, 0, 0, E->res, nullptr, 4, s);
+        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, E->part_plaq, 0, nullptr, E->st, E->fin_cnt,
+                             E->fin_chunk, 0, 0, E->res, nullptr, 4, s);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -497,7 +511,8 @@ su2_status measure_polyakov(su2_ensemble_s *E, int l, double *out) {
     }
     {
         Timed t(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, nullptr, 0, E->part_poly, E->st, 0, 0, nullptr, E->res, 4, s);
+        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, nullptr, 0, E->part_poly, E->st, E->fin_cnt,
+                             E->fin_chunk, 0, 0, nullptr, E->res, 4, s);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -584,6 +599,7 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
 
 su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, int nl) {
     if (block < 64 || block > 256 || (block & 63)) return SU2_EINVAL;
+    if (E->waves != 0 && E->waves != 8) return SU2_EINVAL;
     if (grid < 0 || (grid & 7)) return SU2_EINVAL;
     if (remap != 0 && remap != 1) return SU2_EINVAL;
     if (nl != 1 && nl != 2 && nl != 4) return SU2_EINVAL;
@@ -601,7 +617,7 @@ su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, 
 
 // Time one sweep per candidate shape; links, sweep counter and tries are
 // restored afterwards.
-struct Shape { int block, grid, remap, nl; };
+struct Shape { int block, grid, remap, nl, waves; };
 std::map<std::string, Shape> g_tune_cache;
 
 su2_status autotune_common(su2_ensemble_s *E) {
@@ -609,8 +625,10 @@ su2_status autotune_common(su2_ensemble_s *E) {
     std::snprintf(key, sizeof key, "%s:n%d:sites%lld:t%lld", E->f32 ? "f32" : "f64", E->n, E->total_sites,
                   (long long)E->hdesc[0].n[3]);
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end())
+    if (it != g_tune_cache.end()) {
+        E->waves = it->second.waves;
         return set_launch_common(E, it->second.block, it->second.grid, it->second.remap, it->second.nl);
+    }
 
     hipStream_t s = E->stream();
     void *backup = nullptr;
@@ -624,35 +642,46 @@ su2_status autotune_common(su2_ensemble_s *E) {
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     const bool timing0 = E->timing;
     E->timing = false;
+    CHK(ensure_series(E, 4));
 
     const int blocks[] = {64, 128, 256};
     const int gmul[] = {0, 4, 8, 16};
     const int nls[] = {1, 2, 4};
+    const int wvs[] = {0, 8};
     hipEvent_t ea, eb;
     HIPCHK(hipEventCreate(&ea));
     HIPCHK(hipEventCreate(&eb));
     float best = 1e30f;
-    Shape bestc{E->block, E->grid, E->remap, E->nl};
-    for (int nl : nls)
-        for (int b : blocks)
-            for (int gm : gmul)
-                for (int rm = 0; rm < 2; ++rm) {
-                    const int g = gm ? gm * cus / 8 * 8 : 0;
-                    CHK(set_launch_common(E, b, g, rm, nl));
-                    CHK(enqueue_sweep(E, 0, s));  // warm-up
-                    HIPCHK(hipEventRecord(ea, s));
-                    for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 0, s));
-                    HIPCHK(hipEventRecord(eb, s));
-                    HIPCHK(hipEventSynchronize(eb));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, ea, eb));
-                    if (ms < best) {
-                        best = ms;
-                        bestc = Shape{b, g, rm, nl};
+    Shape bestc{E->block, E->grid, E->remap, E->nl, E->waves};
+    for (int wv : wvs) {
+        if (wv && !E->f32) continue;
+        for (int nl : nls)
+            for (int b : blocks)
+                for (int gm : gmul)
+                    for (int rm = 0; rm < 2; ++rm) {
+                        const int g = gm ? gm * cus / 8 * 8 : 0;
+                        E->waves = wv;
+                        CHK(set_launch_common(E, b, g, rm, nl));
+                        // series slots 0..3 of this candidate's four sweeps
+                        E->hst = st0;
+                        E->hst.run_base = st0.sweep;
+                        CHK(upload_state(E));
+                        CHK(enqueue_sweep(E, 1, s));  // warm-up (with the plaquette series)
+                        HIPCHK(hipEventRecord(ea, s));
+                        for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 1, s));
+                        HIPCHK(hipEventRecord(eb, s));
+                        HIPCHK(hipEventSynchronize(eb));
+                        float ms = 0.f;
+                        HIPCHK(hipEventElapsedTime(&ms, ea, eb));
+                        if (ms < best) {
+                            best = ms;
+                            bestc = Shape{b, g, rm, nl, wv};
+                        }
                     }
-                }
+    }
     HIPCHK(hipEventDestroy(ea));
     HIPCHK(hipEventDestroy(eb));
+    E->waves = bestc.waves;
     CHK(set_launch_common(E, bestc.block, bestc.grid, bestc.remap, bestc.nl));
     HIPCHK(hipMemcpyAsync(E->links, backup, E->link_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, s));
@@ -803,17 +832,25 @@ su2_status su2_ensemble_stats(su2_ensemble E, uint64_t *tries, uint64_t *updates
     return stats_common(E, tries, updates, nullptr);
 }
 
-su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap, int links_per_lane) {
+su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap, int links_per_lane,
+                                   int waves_per_simd) {
     CHK(enter(E));
-    return set_launch_common(E, block, grid, xcd_remap, links_per_lane);
+    if (waves_per_simd != 0 && waves_per_simd != 8) return SU2_EINVAL;
+    const int w0 = E->waves;
+    E->waves = waves_per_simd;
+    su2_status st = set_launch_common(E, block, grid, xcd_remap, links_per_lane);
+    if (st != SU2_OK) E->waves = w0;
+    return st;
 }
 
-su2_status su2_ensemble_get_launch(su2_ensemble E, int *block, int *grid, int *xcd_remap, int *links_per_lane) {
+su2_status su2_ensemble_get_launch(su2_ensemble E, int *block, int *grid, int *xcd_remap, int *links_per_lane,
+                                   int *waves_per_simd) {
     CHK(enter(E));
     if (block) *block = E->block;
     if (grid) *grid = E->grid;
     if (xcd_remap) *xcd_remap = E->remap;
     if (links_per_lane) *links_per_lane = E->nl;
+    if (waves_per_simd) *waves_per_simd = E->waves;
     return SU2_OK;
 }
 
@@ -891,7 +928,7 @@ su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int m
     {
         Timed t(E, SU2_K_HEATBATH, s);
         su2::launch_heatbath(kargs(E, 3), E->f32, mu, parity, E->nl, E->block, E->grid, s, E->trace != nullptr,
-                             false);
+                             false, E->waves);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -1123,12 +1160,13 @@ su2_status su2_load(const char *path, su2_lattice *out) {
     return SU2_OK;
 }
 
-su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap, int links_per_lane) {
-    return su2_ensemble_set_launch(E, block, grid, remap, links_per_lane);
+su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap, int links_per_lane, int waves_per_simd) {
+    return su2_ensemble_set_launch(E, block, grid, remap, links_per_lane, waves_per_simd);
 }
 
-su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap, int *links_per_lane) {
-    return su2_ensemble_get_launch(E, block, grid, remap, links_per_lane);
+su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap, int *links_per_lane,
+                          int *waves_per_simd) {
+    return su2_ensemble_get_launch(E, block, grid, remap, links_per_lane, waves_per_simd);
 }
 
 su2_status su2_autotune(su2_lattice E, double beta) {

@@ -22,7 +22,7 @@ struct KArgs {
 };
 
 void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
-                     bool trace, bool plaq);
+                     bool trace, bool plaq, int waves);
 void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s);
 void launch_init(const KArgs &a, bool f32, int hot, int block, int grid, hipStream_t s);
 void launch_from_canon(const KArgs &a, bool f32, const double *canon, int block, hipStream_t s);
@@ -31,11 +31,15 @@ void launch_to_canon(const KArgs &a, bool f32, const void *src, int ndir, double
 void launch_unit_defect(const KArgs &a, bool f32, unsigned long long *out, int block, hipStream_t s);
 void launch_plaquette(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
 void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
+// Final reduction of plaquette / Polyakov partials: `chunks` workgroups
+// per lattice, cnt[nlat] arrival tickets (zero between launches), chunk
+// scratch of 6 doubles per workgroup.
 // pp: plaquette partials of k_plaquette (4 per tile) or, with pp_hb, of
-// the heat-bath substeps (6 per heat-bath tile); pl: Polyakov partials.
-void launch_finalize(const LatDesc *desc, int nlat, const double *pp, int pp_hb, const double *pl,
-                     DevState *st, int series, int bump, double *outp, double *outl, long long ostride,
-                     hipStream_t s);
+// the heat-bath substeps (3 slots x 4 wavefronts per heat-bath tile,
+// unused wavefront entries zero); pl: Polyakov partials.
+void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp, int pp_hb, const double *pl,
+                     DevState *st, unsigned *cnt, double *chunk, int series, int bump, double *outp, double *outl,
+                     long long ostride, hipStream_t s);
 void launch_bump(DevState *st, hipStream_t s);
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s);

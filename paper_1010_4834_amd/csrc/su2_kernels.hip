@@ -94,7 +94,7 @@ __device__ __forceinline__ void sts_(const Blocks<T, NDIR> &B, int mu, int p, ui
 // 18 link loads; 7 distinct per update once shared with neighbouring lanes.
 template <class T, int MU>
 __device__ __forceinline__ Q<T> staple(const LatDesc &d, const Blocks<T, 4> &B, const Site &S, int par,
-                                       Q<T> (*Vlow)[3] = nullptr) {
+                                       Q<T> *Vlow = nullptr) {
     const int op = par ^ 1;
     const int s_mu = S.s + step_fwd(d, S, MU);
     Q<T> V{T(0), T(0), T(0), T(0)};
@@ -109,11 +109,12 @@ __device__ __forceinline__ Q<T> staple(const LatDesc &d, const Blocks<T, 4> &B, 
         const Q<T> E = lds_(B, MU, op, (uint32_t)(S.s + bn) >> 1);
         const Q<T> F = lds_(B, nu, op, (uint32_t)(S.s + bn) >> 1);
         if (Vlow && nu < MU) {
-            // staple of plane (nu, MU) kept apart for the fused plaquette
+            // staples of the planes (nu, MU), nu < MU, also summed apart
+            // for the fused plaquette
             Q<T> P{T(0), T(0), T(0), T(0)};
             qmul_acc(P, A, qdag(qmul(C, Bm)));
             qmul_acc(P, qdag(qmul(E, D)), F);
-            (*Vlow)[nu] = P;
+            qacc(*Vlow, P);
             qacc(V, P);
         } else {
             qmul_acc(V, A, qdag(qmul(C, Bm)));
@@ -161,9 +162,10 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
 // its other links are final; 1/2 Tr(U' (upper + lower staple of plane nu))
 // over nu < MU and over the three odd substeps MU = 1, 2, 3 is therefore the
 // plaquette sum (paper Sec. 2, eq. for <P>) of the configuration at the end
-// of the sweep.  Slot MU-1 of the tile's six partials holds it.
-template <class T, int MU, bool TRACE, int NL, bool PLAQ>
-__global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
+// of the sweep; by linearity only the summed staple of those planes is
+// kept.  Each wavefront writes its binary64 sum to slot MU-1 of its tile.
+template <class T, int MU, bool TRACE, int NL, bool PLAQ, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_heatbath(KArgs a, int par) {
     using M = Mth<T>;
     const uint32_t sweep = uni(a.st->sweep);
     const uint32_t k0 = uni((unsigned)a.st->seed), k1 = uni((unsigned)(a.st->seed >> 32));
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
         int sidx[NL];
         T alpha[NL];
         Q<T> Wd[NL];
-        Q<T> Vl[NL][3];  // per-plane staples nu < MU (PLAQ only)
+        Q<T> Vl[NL];  // summed staples of the planes nu < MU (PLAQ only)
         uint32_t pend = 0;
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
@@ -188,6 +190,7 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             if (cb < d.vh) {
                 pend |= 1u << m;
                 const Site S = site_of(d, cb, par);
+                Vl[m] = Q<T>{T(0), T(0), T(0), T(0)};
                 const Q<T> V = staple<T, MU>(d, B, S, par, PLAQ ? &Vl[m] : nullptr);
                 const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
                 T k, ik;
@@ -270,23 +273,15 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
                 sts_(B, MU, par, (uint32_t)cb, Un);
                 if (TRACE) a.trace[d.toff + (long long)sidx[m] * 4 + MU] = rec[m];
                 tries += rec[m] & 0x7FFFFFFFu;
-                if (PLAQ) {
-#pragma unroll
-                    for (int nu = 0; nu < MU; ++nu) {  // 1/2 Re Tr(U' V_nu)
-                        const Q<T> &P = Vl[m][nu];
-                        pq += (double)(Un.a * P.a - Un.b * P.b - Un.c * P.c - Un.d * P.d);
-                    }
-                }
+                if (PLAQ)  // 1/2 Re Tr(U' V_low)
+                    pq += (double)(Un.a * Vl[m].a - Un.b * Vl[m].b - Un.c * Vl[m].c - Un.d * Vl[m].d);
             }
         }
         if (PLAQ) {
-            __shared__ DD lds[4];
-            DD acc[1] = {{pq, 0.0}};
-            dd_block_sum<1>(acc, lds);
-            if (threadIdx.x == 0) {
-                a.plaq_part[6 * tile + 2 * (MU - 1)] = acc[0].hi;
-                a.plaq_part[6 * tile + 2 * (MU - 1) + 1] = acc[0].lo;
-            }
+#pragma unroll
+            for (int k = 32; k >= 1; k >>= 1) pq += __shfl_xor(pq, k, 64);
+            if ((threadIdx.x & 63) == 0)
+                a.plaq_part[(3 * (long long)tile + (MU - 1)) * 4 + (threadIdx.x >> 6)] = pq;
         }
         tries = wave_sum_u32(tries);
         if ((threadIdx.x & 63) == 0 && tries) atomicAdd(&a.tries_part[tile], (unsigned long long)tries);
@@ -502,62 +497,144 @@ __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
     });
 }
 
-// Final per-lattice reduction of tile partials in a fixed order; block l
-// handles lattice l.  Plaquette (avg, spatial, temporal) and/or Polyakov.
-// series: write slot (sweep - run_base) of out[l * ostride + slot] and, when
-// `bump`, the last block to arrive advances the sweep counter (every block
-// has read it before arriving).
+// Final per-lattice reduction of tile partials in a fixed order.
+// Workgroup b handles chunk b % C of lattice b / C: it sums its share of
+// the lattice's tile partials, writes a (hi, lo) pair per quantity to
+// `chunk`, and the last chunk of the lattice to arrive (ticket in cnt[l])
+// combines the C pairs in chunk order and writes the result:
+//   plaquette (avg, spatial, temporal) or its series value, Polyakov loop.
+// series: slot (sweep - run_base) of out[l * ostride + slot]; with `bump`,
+// the last lattice to finish advances the sweep counter.
+// Plaquette partials: k_plaquette's (spatial, temporal) pairs per tile, or
+// with pp_hb the heat-bath substeps' [tile][slot 0,1 spatial, 2 temporal]
+// [wavefront] binary64 sums.  Polyakov partials: one pair per spatial tile.
+__device__ __forceinline__ void chunk_range(int n, int C, int c, int &lo, int &hi) {
+    lo = (int)(((long long)n * c) / C);
+    hi = (int)(((long long)n * (c + 1)) / C);
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const double *pp, int pp_hb,
-                                                  const double *pl, DevState *st, int series, int bump,
-                                                  double *outp, double *outl, long long ostride) {
-    __shared__ DD lds[2 * 4];
-    const LatDesc d = load_desc(desc + blockIdx.x);
+                                                  const double *pl, DevState *st, unsigned *cnt, double *chunk,
+                                                  int C, int series, int bump, double *outp, double *outl,
+                                                  long long ostride) {
+    __shared__ DD lds[3 * 4];
+    __shared__ int last;
+    last = 1;
+    const int l = blockIdx.x / C, c = blockIdx.x % C;
+    const LatDesc d = load_desc(desc + l);
     const unsigned sweep = uni(st->sweep);
-    const long long idx = series ? (long long)(sweep - uni(st->run_base)) : 0;
-    const double V = 2.0 * (double)d.vh;
-    if (pp) {
-        DD acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
-        if (pp_hb) {  // heat-bath partials: slots 0, 1 spatial planes, 2 temporal
-            for (int t = threadIdx.x; t < d.nmtile; t += blockDim.x) {
-                const double *q = pp + 6 * (long long)(d.mtile0 + t);
-                acc[0] = dd_add(dd_add(acc[0], DD{q[0], q[1]}), DD{q[2], q[3]});
-                acc[1] = dd_add(acc[1], DD{q[4], q[5]});
+    // four independent compensated accumulators per quantity (the sums are
+    // latency bound), combined in a fixed order
+    DD a4[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a4[u][k] = DD{0.0, 0.0};
+    if (pp && pp_hb) {
+        int lo, hi;
+        chunk_range(d.nmtile, C, c, lo, hi);
+        const double4 *q4 = reinterpret_cast<const double4 *>(pp) + 3 * (long long)d.mtile0;
+        for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
+            double4 v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    v[u][k] = t < hi ? q4[3 * (long long)t + k] : make_double4(0.0, 0.0, 0.0, 0.0);
             }
-        } else {
-            for (int t = threadIdx.x; t < d.ntile; t += blockDim.x) {
-                const double *q = pp + 4 * (long long)(d.tile0 + t);
-                acc[0] = dd_add(acc[0], DD{q[0], q[1]});
-                acc[1] = dd_add(acc[1], DD{q[2], q[3]});
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    DD &x = a4[u][k == 2 ? 1 : 0];
+                    x = dd_add(x, DD{(v[u][k].x + v[u][k].y), 0.0});
+                    x = dd_add(x, DD{(v[u][k].z + v[u][k].w), 0.0});
+                }
+        }
+    } else if (pp) {
+        int lo, hi;
+        chunk_range(d.ntile, C, c, lo, hi);
+        for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                if (t < hi) {
+                    const double4 q = reinterpret_cast<const double4 *>(pp)[d.tile0 + (long long)t];
+                    a4[u][0] = dd_add(a4[u][0], DD{q.x, q.y});
+                    a4[u][1] = dd_add(a4[u][1], DD{q.z, q.w});
+                }
             }
         }
-        dd_block_sum<2>(acc, lds);
+    }
+    if (pl) {
+        int lo, hi;
+        chunk_range(d.nstile, C, c, lo, hi);
+        for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                if (t < hi) {
+                    const double2 q = reinterpret_cast<const double2 *>(pl)[d.stile0 + (long long)t];
+                    a4[u][2] = dd_add(a4[u][2], DD{q.x, q.y});
+                }
+            }
+        }
+    }
+    DD acc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = dd_add(dd_add(a4[0][k], a4[1][k]), dd_add(a4[2][k], a4[3][k]));
+    dd_block_sum<3>(acc, lds);
+    if (C > 1) {  // chunk sums meet in the last chunk of the lattice to arrive
         if (threadIdx.x == 0) {
-            const double sp = acc[0].hi + acc[0].lo, tp = acc[1].hi + acc[1].lo;
+            double *ch = chunk + 6 * (long long)blockIdx.x;
+            for (int k = 0; k < 3; ++k) {
+                ch[2 * k] = acc[k].hi;
+                ch[2 * k + 1] = acc[k].lo;
+            }
+            __threadfence();
+            last = atomicAdd(&cnt[l], 1u) == (unsigned)(C - 1);
+        }
+        __syncthreads();
+        if (!last) return;
+    }
+    if (threadIdx.x == 0) {
+        DD tot[3] = {acc[0], acc[1], acc[2]};
+        if (C > 1) {
+            __threadfence();
+            const volatile double *ch = chunk + 6 * (long long)l * C;
+            for (int k = 0; k < 3; ++k) tot[k] = DD{0.0, 0.0};
+            for (int cc = 0; cc < C; ++cc)
+                for (int k = 0; k < 3; ++k)
+                    tot[k] = dd_add(tot[k], DD{ch[6 * cc + 2 * k], ch[6 * cc + 2 * k + 1]});
+            cnt[l] = 0u;
+        }
+        const long long idx = series ? (long long)(sweep - uni(st->run_base)) : 0;
+        const double V = 2.0 * (double)d.vh;
+        const double sp = tot[0].hi + tot[0].lo, tp = tot[1].hi + tot[1].lo;
+        if (pp) {
             if (series) {
-                outp[blockIdx.x * ostride + idx] = (sp + tp) / (6.0 * V);
+                outp[l * ostride + idx] = (sp + tp) / (6.0 * V);
             } else {
-                double *o = outp + blockIdx.x * ostride;
+                double *o = outp + l * ostride;
                 o[0] = (sp + tp) / (6.0 * V);
                 o[1] = sp / (3.0 * V);
                 o[2] = tp / (3.0 * V);
             }
         }
-    }
-    if (pl) {
-        DD acc[1] = {{0.0, 0.0}};
-        for (int t = threadIdx.x; t < d.nstile; t += blockDim.x) {
-            const double *q = pl + 2 * (long long)(d.stile0 + t);
-            acc[0] = dd_add(acc[0], DD{q[0], q[1]});
-        }
-        dd_block_sum<1>(acc, lds);
-        if (threadIdx.x == 0) outl[blockIdx.x * ostride + idx] = (acc[0].hi + acc[0].lo) / (double)d.ns;
-    }
-    if (bump && threadIdx.x == 0) {
-        __threadfence();
-        const unsigned ticket = atomicAdd(&st->done, 1u);
-        if (ticket == gridDim.x - 1) {
-            st->done = 0u;
-            st->sweep = sweep + 1u;
+        if (pl) outl[l * ostride + idx] = (tot[2].hi + tot[2].lo) / (double)d.ns;
+        if (bump) {
+            const unsigned nlat = gridDim.x / C;
+            if (nlat == 1) {
+                st->sweep = sweep + 1u;
+            } else {
+                __threadfence();
+                const unsigned ticket = atomicAdd(&st->done, 1u);
+                if (ticket == nlat - 1) {
+                    st->done = 0u;
+                    st->sweep = sweep + 1u;
+                }
+            }
         }
     }
 }
@@ -746,45 +823,59 @@ static inline dim3 grid_of(const KArgs &a, int grid) {
     return dim3((unsigned)g);
 }
 
-template <class T, int MU, int NL>
-static void launch_hb_nl(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq) {
+template <class T, int MU, int NL, int W>
+static void launch_hb_w(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq) {
     const dim3 g = grid_of(a, grid), b(block);
     if (plaq) {
         if constexpr (MU >= 1) {
-            if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, true>), g, b, 0, s, a, par);
-            else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, true>), g, b, 0, s, a, par);
+            if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, true, W>), g, b, 0, s, a, par);
+            else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, true, W>), g, b, 0, s, a, par);
         }
     } else {
-        if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, false>), g, b, 0, s, a, par);
-        else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, false>), g, b, 0, s, a, par);
+        if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, false, W>), g, b, 0, s, a, par);
+        else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, false, W>), g, b, 0, s, a, par);
     }
+}
+
+// waves: 8 selects the binary32 build limited to 64 VGPRs (eight
+// wavefronts per SIMD); otherwise the compiler's register allocation.
+template <class T, int MU, int NL>
+static void launch_hb_nl(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq,
+                         int waves) {
+    if constexpr (sizeof(T) == 4) {
+        if (waves == 8 && !trace) {
+            launch_hb_w<T, MU, NL, 8>(a, par, block, grid, s, trace, plaq);
+            return;
+        }
+    }
+    launch_hb_w<T, MU, NL, 1>(a, par, block, grid, s, trace, plaq);
 }
 
 template <class T, int MU>
 static void launch_hb_mu(const KArgs &a, int par, int nl, int block, int grid, hipStream_t s, bool trace,
-                         bool plaq) {
+                         bool plaq, int waves) {
     switch (nl) {
-    case 1: launch_hb_nl<T, MU, 1>(a, par, block, grid, s, trace, plaq); break;
-    case 2: launch_hb_nl<T, MU, 2>(a, par, block, grid, s, trace, plaq); break;
-    default: launch_hb_nl<T, MU, 4>(a, par, block, grid, s, trace, plaq); break;
+    case 1: launch_hb_nl<T, MU, 1>(a, par, block, grid, s, trace, plaq, waves); break;
+    case 2: launch_hb_nl<T, MU, 2>(a, par, block, grid, s, trace, plaq, waves); break;
+    default: launch_hb_nl<T, MU, 4>(a, par, block, grid, s, trace, plaq, waves); break;
     }
 }
 
 template <class T>
 static void launch_hb_t(const KArgs &a, int mu, int par, int nl, int block, int grid, hipStream_t s,
-                        bool trace, bool plaq) {
+                        bool trace, bool plaq, int waves) {
     switch (mu) {
-    case 0: launch_hb_mu<T, 0>(a, par, nl, block, grid, s, trace, false); break;
-    case 1: launch_hb_mu<T, 1>(a, par, nl, block, grid, s, trace, plaq); break;
-    case 2: launch_hb_mu<T, 2>(a, par, nl, block, grid, s, trace, plaq); break;
-    default: launch_hb_mu<T, 3>(a, par, nl, block, grid, s, trace, plaq); break;
+    case 0: launch_hb_mu<T, 0>(a, par, nl, block, grid, s, trace, false, waves); break;
+    case 1: launch_hb_mu<T, 1>(a, par, nl, block, grid, s, trace, plaq, waves); break;
+    case 2: launch_hb_mu<T, 2>(a, par, nl, block, grid, s, trace, plaq, waves); break;
+    default: launch_hb_mu<T, 3>(a, par, nl, block, grid, s, trace, plaq, waves); break;
     }
 }
 
 void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
-                     bool trace, bool plaq) {
-    if (f32) launch_hb_t<float>(a, mu, par, nl, block, grid, s, trace, plaq);
-    else launch_hb_t<double>(a, mu, par, nl, block, grid, s, trace, plaq);
+                     bool trace, bool plaq, int waves) {
+    if (f32) launch_hb_t<float>(a, mu, par, nl, block, grid, s, trace, plaq, waves);
+    else launch_hb_t<double>(a, mu, par, nl, block, grid, s, trace, plaq, waves);
 }
 
 template <class T>
@@ -833,11 +924,11 @@ void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid
     else hipLaunchKernelGGL((k_polyakov<double>), grid_of(a, grid), dim3(block), 0, s, a, part);
 }
 
-void launch_finalize(const LatDesc *desc, int nlat, const double *pp, int pp_hb, const double *pl,
-                     DevState *st, int series, int bump, double *outp, double *outl, long long ostride,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(nlat), dim3(256), 0, s, desc, pp, pp_hb, pl, st, series, bump, outp,
-                       outl, ostride);
+void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp, int pp_hb, const double *pl,
+                     DevState *st, unsigned *cnt, double *chunk, int series, int bump, double *outp, double *outl,
+                     long long ostride, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)(nlat * chunks)), dim3(256), 0, s, desc, pp, pp_hb, pl, st, cnt,
+                       chunk, chunks, series, bump, outp, outl, ostride);
 }
 
 void launch_bump(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, st); }
