@@ -27,6 +27,24 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# Bytes one heat-bath substep moves at 32^4 FP32, from rocprofv3 --pmc runs of
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the eight substeps
+# of a sweep), scaled by 2.0 and 1.0: the factors that make a 1 GiB device
+# copy read back its own size.  Valid only for the kernel sources with this
+# hash and the launch shape the counters were taken with.
+HB_TRAFFIC = {"sources_sha256": "e485f6e28a51593b7106b66adaba28d1c9a27e12cd6d5b92ad24a4ce0801bfb9",
+              "launch": [256, 4096, 1, 1], "bytes": 80215826}
+KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1010_4834_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def configs():
     c3 = [(32, 32, 32, 4)] * 16, [2.1 + 0.4 * i / 15 for i in range(16)]
@@ -75,7 +93,7 @@ def main():
                     help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--launch", default=None,
-                    help="block,grid,xcd_remap,links_per_lane,waves (skips tuning)")
+                    help="block,grid,xcd_remap,links_per_lane (skips tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -100,7 +118,7 @@ def main():
         su2.su2_ensemble_set_launch(ens, *[int(x) for x in args.launch.split(",")])
     elif not args.no_tune:
         su2.su2_ensemble_autotune(ens)
-    block, grid, remap, nl, waves = su2.su2_ensemble_get_launch(ens)
+    block, grid, remap, nl = su2.su2_ensemble_get_launch(ens)
     su2.su2_ensemble_run(ens, n, args.warmup, seed, True, cfg["poly"])
 
     # ---- timed region: K steps, graph replay, one D2H of the series ----
@@ -125,6 +143,10 @@ def main():
     rd_ms, rd_n = su2.su2_ensemble_get_timing(ens, su2.K_REDUCE)
     su2.su2_ensemble_set_timing(ens, 0)
     hb_avg_us = 1e3 * hb_ms / hb_n
+    traffic = None
+    if (args.config == "c2" and HB_TRAFFIC["bytes"] and [block, grid, remap, nl] == HB_TRAFFIC["launch"]
+            and kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]):
+        traffic = HB_TRAFFIC["bytes"]
     link_b = 16
     hb_bytes = (updates_per_step // 8) * 8 * link_b   # per substep: V/2 updates x 128 B
     achieved = hb_bytes / (hb_avg_us * 1e-6) / 1e9
@@ -148,9 +170,9 @@ def main():
                    "links": "binary32, binary64 reductions and norm", "sweeps_per_step": 1,
                    "sampler": "Kennedy-Pendleton (alpha>=2) / Creutz",
                    "launch": {"block": block, "grid": grid, "xcd_remap": remap,
-                              "links_per_lane": nl, "waves_per_simd": waves}},
+                              "links_per_lane": nl}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_heatbath<float> (one checkerboard substep)",
                      "bytes_per_launch": hb_bytes, "avg_launch_us": hb_avg_us},
         "other_kernels_us": {"polyakov": 1e3 * po_ms / max(po_n, 1),

@@ -184,19 +184,18 @@ su2_status su2_load(const char *path, su2_lattice *out);
 /* Launch shape: threads per workgroup (64, 128, 192 or 256), resident
  * workgroups of the persistent grid (0 = one workgroup per tile; else a
  * multiple of 8), whether tiles are laid out per XCD (1) or round-robin (0),
- * heat-bath links per lane (1, 2 or 4: a lane draws its links in one
- * rejection loop) and waves per SIMD (0: the compiler's register use; 8:
- * the binary32 heat bath built for 64 VGPRs).  Results do not depend on it. */
-su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap, int links_per_lane,
-                          int waves_per_simd);
-su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap, int *links_per_lane,
-                          int *waves_per_simd);
+ * and heat-bath links per lane (1, 2 or 4: a lane draws its links in one
+ * rejection loop).  Results do not depend on it.  EINVAL for other values. */
+su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap, int links_per_lane);
+su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap, int *links_per_lane);
 /* Time the candidate launch shapes on this lattice and keep the fastest
  * (the links are saved and restored around the trial sweeps). */
 su2_status su2_autotune(su2_lattice lat, double beta);
 
 /* Per-kernel timing with HIP events on the handle's stream (enable = 1
- * also disables graph replay so every kernel is bracketed).  get_timing
+ * also disables graph replay so every kernel is timed).  Heat-bath launches
+ * have their events stamped by the launch itself with the kernel's start
+ * and end; the other kernels are bracketed by event records.  get_timing
  * returns the summed milliseconds and launch count since enabling. */
 su2_status su2_set_timing(su2_lattice lat, int enable);
 su2_status su2_get_timing(su2_lattice lat, su2_kernel_kind kind, double *ms, int64_t *launches);
@@ -225,9 +224,9 @@ su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
 su2_status su2_ensemble_set_links(su2_ensemble ens, int i, const double *host);
 su2_status su2_ensemble_stats(su2_ensemble ens, uint64_t *tries, uint64_t *updates);
 su2_status su2_ensemble_set_launch(su2_ensemble ens, int block, int grid, int xcd_remap,
-                                   int links_per_lane, int waves_per_simd);
+                                   int links_per_lane);
 su2_status su2_ensemble_get_launch(su2_ensemble ens, int *block, int *grid, int *xcd_remap,
-                                   int *links_per_lane, int *waves_per_simd);
+                                   int *links_per_lane);
 su2_status su2_ensemble_autotune(su2_ensemble ens);
 su2_status su2_ensemble_set_timing(su2_ensemble ens, int enable);
 su2_status su2_ensemble_get_timing(su2_ensemble ens, su2_kernel_kind kind, double *ms,

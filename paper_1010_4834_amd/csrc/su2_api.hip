@@ -48,7 +48,7 @@ struct su2_ensemble_s {
     long long total_links = 0;  // 4 * sum V
     long long total_sites = 0;
 
-    int block = 256, grid = 0, remap = 1, nl = 1, waves = 0;
+    int block = 256, grid = 0, remap = 1, nl = 1;
     std::vector<Tile> htiles, hstiles, hvtiles, hmtiles;
     Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr, *mtiles = nullptr;
     int ntiles = 0, nstiles = 0, nvtiles = 0, nmtiles = 0;
@@ -192,16 +192,24 @@ struct Timed {
     su2_ensemble_s *E;
     int kind;
     hipEvent_t a = nullptr, b = nullptr;
-    Timed(su2_ensemble_s *e, int k, hipStream_t s) : E(e), kind(k) {
+    bool stamped;
+    // stamped: the launch itself stamps a and b with the kernel's start and
+    // end (see ev()); otherwise a and b are recorded on the stream around it.
+    Timed(su2_ensemble_s *e, int k, hipStream_t s, bool stamp = false) : E(e), kind(k), stamped(stamp) {
         if (E->timing) {
             a = take_event(E);
             b = take_event(E);
-            if (a) (void)hipEventRecord(a, s);
+            if (a && !stamped) (void)hipEventRecord(a, s);
         }
+    }
+    su2::Ev ev() const {
+        su2::Ev v;
+        if (E->timing && a && b) v.a = a, v.b = b;
+        return v;
     }
     void done(hipStream_t s) {
         if (E->timing && a && b) {
-            (void)hipEventRecord(b, s);
+            if (!stamped) (void)hipEventRecord(b, s);
             E->pending.push_back(EventPair{kind, a, b});
         }
     }
@@ -408,9 +416,9 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
-            Timed t(E, SU2_K_HEATBATH, s);
+            Timed t(E, SU2_K_HEATBATH, s, true);
             su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq,
-                                 E->waves);
+                                 t.ev());
             t.done(s);
         }
     if (meas & 2) {
@@ -599,7 +607,6 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
 
 su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, int nl) {
     if (block < 64 || block > 256 || (block & 63)) return SU2_EINVAL;
-    if (E->waves != 0 && E->waves != 8) return SU2_EINVAL;
     if (grid < 0 || (grid & 7)) return SU2_EINVAL;
     if (remap != 0 && remap != 1) return SU2_EINVAL;
     if (nl != 1 && nl != 2 && nl != 4) return SU2_EINVAL;
@@ -617,7 +624,7 @@ su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, 
 
 // Time one sweep per candidate shape; links, sweep counter and tries are
 // restored afterwards.
-struct Shape { int block, grid, remap, nl, waves; };
+struct Shape { int block, grid, remap, nl; };
 std::map<std::string, Shape> g_tune_cache;
 
 su2_status autotune_common(su2_ensemble_s *E) {
@@ -626,7 +633,6 @@ su2_status autotune_common(su2_ensemble_s *E) {
                   (long long)E->hdesc[0].n[3]);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-        E->waves = it->second.waves;
         return set_launch_common(E, it->second.block, it->second.grid, it->second.remap, it->second.nl);
     }
 
@@ -647,41 +653,35 @@ su2_status autotune_common(su2_ensemble_s *E) {
     const int blocks[] = {64, 128, 256};
     const int gmul[] = {0, 4, 8, 16};
     const int nls[] = {1, 2, 4};
-    const int wvs[] = {0, 8};
     hipEvent_t ea, eb;
     HIPCHK(hipEventCreate(&ea));
     HIPCHK(hipEventCreate(&eb));
     float best = 1e30f;
-    Shape bestc{E->block, E->grid, E->remap, E->nl, E->waves};
-    for (int wv : wvs) {
-        if (wv && !E->f32) continue;
-        for (int nl : nls)
-            for (int b : blocks)
-                for (int gm : gmul)
-                    for (int rm = 0; rm < 2; ++rm) {
-                        const int g = gm ? gm * cus / 8 * 8 : 0;
-                        E->waves = wv;
-                        CHK(set_launch_common(E, b, g, rm, nl));
-                        // series slots 0..3 of this candidate's four sweeps
-                        E->hst = st0;
-                        E->hst.run_base = st0.sweep;
-                        CHK(upload_state(E));
-                        CHK(enqueue_sweep(E, 1, s));  // warm-up (with the plaquette series)
-                        HIPCHK(hipEventRecord(ea, s));
-                        for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 1, s));
-                        HIPCHK(hipEventRecord(eb, s));
-                        HIPCHK(hipEventSynchronize(eb));
-                        float ms = 0.f;
-                        HIPCHK(hipEventElapsedTime(&ms, ea, eb));
-                        if (ms < best) {
-                            best = ms;
-                            bestc = Shape{b, g, rm, nl, wv};
-                        }
+    Shape bestc{E->block, E->grid, E->remap, E->nl};
+    for (int nl : nls)
+        for (int b : blocks)
+            for (int gm : gmul)
+                for (int rm = 0; rm < 2; ++rm) {
+                    const int g = gm ? gm * cus / 8 * 8 : 0;
+                    CHK(set_launch_common(E, b, g, rm, nl));
+                    // series slots 0..3 of this candidate's four sweeps
+                    E->hst = st0;
+                    E->hst.run_base = st0.sweep;
+                    CHK(upload_state(E));
+                    CHK(enqueue_sweep(E, 1, s));  // warm-up (with the plaquette series)
+                    HIPCHK(hipEventRecord(ea, s));
+                    for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 1, s));
+                    HIPCHK(hipEventRecord(eb, s));
+                    HIPCHK(hipEventSynchronize(eb));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, ea, eb));
+                    if (ms < best) {
+                        best = ms;
+                        bestc = Shape{b, g, rm, nl};
                     }
-    }
+                }
     HIPCHK(hipEventDestroy(ea));
     HIPCHK(hipEventDestroy(eb));
-    E->waves = bestc.waves;
     CHK(set_launch_common(E, bestc.block, bestc.grid, bestc.remap, bestc.nl));
     HIPCHK(hipMemcpyAsync(E->links, backup, E->link_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, s));
@@ -832,25 +832,17 @@ su2_status su2_ensemble_stats(su2_ensemble E, uint64_t *tries, uint64_t *updates
     return stats_common(E, tries, updates, nullptr);
 }
 
-su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap, int links_per_lane,
-                                   int waves_per_simd) {
+su2_status su2_ensemble_set_launch(su2_ensemble E, int block, int grid, int xcd_remap, int links_per_lane) {
     CHK(enter(E));
-    if (waves_per_simd != 0 && waves_per_simd != 8) return SU2_EINVAL;
-    const int w0 = E->waves;
-    E->waves = waves_per_simd;
-    su2_status st = set_launch_common(E, block, grid, xcd_remap, links_per_lane);
-    if (st != SU2_OK) E->waves = w0;
-    return st;
+    return set_launch_common(E, block, grid, xcd_remap, links_per_lane);
 }
 
-su2_status su2_ensemble_get_launch(su2_ensemble E, int *block, int *grid, int *xcd_remap, int *links_per_lane,
-                                   int *waves_per_simd) {
+su2_status su2_ensemble_get_launch(su2_ensemble E, int *block, int *grid, int *xcd_remap, int *links_per_lane) {
     CHK(enter(E));
     if (block) *block = E->block;
     if (grid) *grid = E->grid;
     if (xcd_remap) *xcd_remap = E->remap;
     if (links_per_lane) *links_per_lane = E->nl;
-    if (waves_per_simd) *waves_per_simd = E->waves;
     return SU2_OK;
 }
 
@@ -926,9 +918,9 @@ su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int m
     CHK(set_seed(E, seed));
     hipStream_t s = E->stream();
     {
-        Timed t(E, SU2_K_HEATBATH, s);
+        Timed t(E, SU2_K_HEATBATH, s, true);
         su2::launch_heatbath(kargs(E, 3), E->f32, mu, parity, E->nl, E->block, E->grid, s, E->trace != nullptr,
-                             false, E->waves);
+                             false, t.ev());
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -1160,13 +1152,12 @@ su2_status su2_load(const char *path, su2_lattice *out) {
     return SU2_OK;
 }
 
-su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap, int links_per_lane, int waves_per_simd) {
-    return su2_ensemble_set_launch(E, block, grid, remap, links_per_lane, waves_per_simd);
+su2_status su2_set_launch(su2_lattice E, int block, int grid, int remap, int links_per_lane) {
+    return su2_ensemble_set_launch(E, block, grid, remap, links_per_lane);
 }
 
-su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap, int *links_per_lane,
-                          int *waves_per_simd) {
-    return su2_ensemble_get_launch(E, block, grid, remap, links_per_lane, waves_per_simd);
+su2_status su2_get_launch(su2_lattice E, int *block, int *grid, int *remap, int *links_per_lane) {
+    return su2_ensemble_get_launch(E, block, grid, remap, links_per_lane);
 }
 
 su2_status su2_autotune(su2_lattice E, double beta) {

@@ -293,18 +293,30 @@ __device__ __forceinline__ Tile load_tile(const Tile *t, int i) {
 // b % 8 (round-robin dispatch) and is given tiles from that XCD's
 // contiguous eighth of the tile list, so neighbouring tiles (which share
 // staple links) meet in the same L2.
+struct TileWalk {
+    int base, i, step, lim;
+    __device__ __forceinline__ TileWalk(int ntiles, int xcd_remap) {
+        const int G = gridDim.x, b = blockIdx.x;
+        base = 0, i = b, step = G, lim = ntiles;
+        if (xcd_remap && (G & 7) == 0) {
+            const int tx = (ntiles + 7) >> 3;  // tiles per XCD
+            base = (b & 7) * tx;
+            i = b >> 3;
+            step = G >> 3;
+            lim = min(tx, ntiles - base);
+        }
+    }
+    __device__ __forceinline__ bool ok() const { return i < lim; }
+    __device__ __forceinline__ int tile() const { return base + i; }
+    __device__ __forceinline__ bool next() {
+        i += step;
+        return i < lim;
+    }
+};
+
 template <class F>
 __device__ __forceinline__ void for_each_tile(int ntiles, int xcd_remap, F &&body) {
-    const int G = gridDim.x, b = blockIdx.x;
-    int base = 0, i = b, step = G, lim = ntiles;
-    if (xcd_remap && (G & 7) == 0) {
-        const int tx = (ntiles + 7) >> 3;  // tiles per XCD
-        base = (b & 7) * tx;
-        i = b >> 3;
-        step = G >> 3;
-        lim = min(tx, ntiles - base);
-    }
-    for (; i < lim; i += step) body(base + i);
+    for (TileWalk w(ntiles, xcd_remap); w.ok(); w.next()) body(w.tile());
 }
 
 }  // namespace su2

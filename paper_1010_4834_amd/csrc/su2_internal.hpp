@@ -21,8 +21,13 @@ struct KArgs {
     int sampler;                         // 0 hybrid, 1 Creutz
 };
 
+// Optional timing events stamped by the launch itself (both null: none).
+struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
 void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
-                     bool trace, bool plaq, int waves);
+                     bool trace, bool plaq, const Ev &ev = Ev{});
 void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s);
 void launch_init(const KArgs &a, bool f32, int hot, int block, int grid, hipStream_t s);
 void launch_from_canon(const KArgs &a, bool f32, const double *canon, int block, hipStream_t s);

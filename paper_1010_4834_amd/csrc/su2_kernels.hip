@@ -8,6 +8,8 @@
 // plus a 32-bit lane offset.  Nothing here is a dense contraction (at most
 // 4x4 real products per quaternion): no MFMA, vector-ALU code fed by
 // coalesced float4 / float64x2 loads of the parity-split layout.
+#include <hip/hip_ext.h>
+
 #include "su2_internal.hpp"
 
 namespace su2 {
@@ -91,26 +93,38 @@ __device__ __forceinline__ void sts_(const Blocks<T, NDIR> &B, int mu, int p, ui
 // weight is exp(beta/2 Tr(U V))).  nu ascending, upper then lower:
 //   upper U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag,
 //   lower U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu).
-// 18 link loads; 7 distinct per update once shared with neighbouring lanes.
+// 18 link loads (gather); 7 distinct per update once shared with
+// neighbouring lanes.  combine() does the arithmetic on the gathered links.
 template <class T, int MU>
-__device__ __forceinline__ Q<T> staple(const LatDesc &d, const Blocks<T, 4> &B, const Site &S, int par,
-                                       Q<T> *Vlow = nullptr) {
+__device__ __forceinline__ void gather(const LatDesc &d, const Blocks<T, 4> &B, const Site &S, int par,
+                                       Q<T> (&L)[18]) {
     const int op = par ^ 1;
     const int s_mu = S.s + step_fwd(d, S, MU);
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU) continue;
+        const int q = 6 * (nu < MU ? nu : nu - 1);
+        const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
+        L[q + 0] = lds_(B, nu, op, (uint32_t)s_mu >> 1);            // U_nu(x+mu)
+        L[q + 1] = lds_(B, MU, op, (uint32_t)(S.s + fn) >> 1);      // U_mu(x+nu)
+        L[q + 2] = lds_(B, nu, par, (uint32_t)S.s >> 1);            // U_nu(x)
+        L[q + 3] = lds_(B, nu, par, (uint32_t)(s_mu + bn) >> 1);    // U_nu(x+mu-nu)
+        L[q + 4] = lds_(B, MU, op, (uint32_t)(S.s + bn) >> 1);      // U_mu(x-nu)
+        L[q + 5] = lds_(B, nu, op, (uint32_t)(S.s + bn) >> 1);      // U_nu(x-nu)
+    }
+}
+
+// Vlow (fused plaquette): the staples of the planes (nu, MU), nu < MU, are
+// also summed apart.
+template <class T, int MU>
+__device__ __forceinline__ Q<T> combine(const Q<T> (&L)[18], Q<T> *Vlow = nullptr) {
     Q<T> V{T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == MU) continue;
-        const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
-        const Q<T> A = lds_(B, nu, op, (uint32_t)s_mu >> 1);
-        const Q<T> Bm = lds_(B, MU, op, (uint32_t)(S.s + fn) >> 1);
-        const Q<T> C = lds_(B, nu, par, (uint32_t)S.s >> 1);
-        const Q<T> D = lds_(B, nu, par, (uint32_t)(s_mu + bn) >> 1);
-        const Q<T> E = lds_(B, MU, op, (uint32_t)(S.s + bn) >> 1);
-        const Q<T> F = lds_(B, nu, op, (uint32_t)(S.s + bn) >> 1);
+        const int q = 6 * (nu < MU ? nu : nu - 1);
+        const Q<T> &A = L[q + 0], &Bm = L[q + 1], &C = L[q + 2], &D = L[q + 3], &E = L[q + 4], &F = L[q + 5];
         if (Vlow && nu < MU) {
-            // staples of the planes (nu, MU), nu < MU, also summed apart
-            // for the fused plaquette
             Q<T> P{T(0), T(0), T(0), T(0)};
             qmul_acc(P, A, qdag(qmul(C, Bm)));
             qmul_acc(P, qdag(qmul(E, D)), F);
@@ -122,6 +136,14 @@ __device__ __forceinline__ Q<T> staple(const LatDesc &d, const Blocks<T, 4> &B, 
         }
     }
     return V;
+}
+
+template <class T, int MU>
+__device__ __forceinline__ Q<T> staple(const LatDesc &d, const Blocks<T, 4> &B, const Site &S, int par,
+                                       Q<T> *Vlow = nullptr) {
+    Q<T> L[18];
+    gather<T, MU>(d, B, S, par, L);
+    return combine<T, MU>(L, Vlow);
 }
 
 template <class T, int N> __device__ __forceinline__ T pick(const T (&a)[N], int m) {
@@ -164,14 +186,17 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
 // plaquette sum (paper Sec. 2, eq. for <P>) of the configuration at the end
 // of the sweep; by linearity only the summed staple of those planes is
 // kept.  Each wavefront writes its binary64 sum to slot MU-1 of its tile.
-template <class T, int MU, bool TRACE, int NL, bool PLAQ, int W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_heatbath(KArgs a, int par) {
+template <class T, int MU, bool TRACE, int NL, bool PLAQ>
+__global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
     using M = Mth<T>;
     const uint32_t sweep = uni(a.st->sweep);
     const uint32_t k0 = uni((unsigned)a.st->seed), k1 = uni((unsigned)(a.st->seed >> 32));
-    for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = load_tile(a.tiles, tile);
-        const LatDesc d = load_desc(a.desc + tl.x);
+    TileWalk w(a.ntiles, a.xcd_remap);
+    if (!w.ok()) return;
+    int tile = w.tile();
+    Tile tl = load_tile(a.tiles, tile);
+    LatDesc d = load_desc(a.desc + tl.x);
+    while (true) {
         const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const uint32_t c2 = tag(d.lat_id, PURPOSE_HEATBATH, MU, par);
         const T beta = (sizeof(T) == 4) ? (T)d.betaf : (T)d.beta;
@@ -189,8 +214,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
             Wd[m] = qone<T>();
             if (cb < d.vh) {
                 pend |= 1u << m;
-                const Site S = site_of(d, cb, par);
                 Vl[m] = Q<T>{T(0), T(0), T(0), T(0)};
+                const Site S = site_of(d, cb, par);
                 const Q<T> V = staple<T, MU>(d, B, S, par, PLAQ ? &Vl[m] : nullptr);
                 const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
                 T k, ik;
@@ -221,11 +246,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
             const int s = pick(sidx, m);
             const T al = pick(alpha, m);
             const bool creutz = (a.sampler == 1) || !(al >= T(2));
-            const uint4 w = philox10((uint32_t)s, sweep, c2, j, k0, k1);
+            const uint4 wd = philox10((uint32_t)s, sweep, c2, j, k0, k1);
             bool acc;
             T dl;
             if (creutz) {
-                const T u1 = M::u(w.x), u2 = M::u(w.y);
+                const T u1 = M::u(wd.x), u2 = M::u(wd.y);
                 if (al >= T(1e-20)) {
                     const T cf = -M::expm1_(T(-2) * al);
                     dl = -M::log1p_(-(T(1) - u1) * cf) / al;
@@ -234,7 +259,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
                 }
                 acc = u2 * u2 <= dl * (T(2) - dl);
             } else {
-                const T r1 = M::u(w.x), r2 = M::u(w.y), r3 = M::u(w.z), r4 = M::u(w.w);
+                const T r1 = M::u(wd.x), r2 = M::u(wd.y), r3 = M::u(wd.z), r4 = M::u(wd.w);
                 const T cs = M::cos2pi(r2);
                 const T lam2 = -(M::ln(r1) + cs * cs * M::ln(r3)) / (T(2) * al);
                 acc = r4 * r4 <= T(1) - lam2;
@@ -261,8 +286,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
         for (int m = 0; m < NL; ++m) {
             const int cb = tl.y + m * (int)blockDim.x + (int)threadIdx.x;
             if (cb < d.vh) {
-                const uint4 w = philox10((uint32_t)sidx[m], sweep, c2, 0xFFFFFFFFu, k0, k1);
-                const T u1 = M::u(w.x), u2 = M::u(w.y);
+                const uint4 wd = philox10((uint32_t)sidx[m], sweep, c2, 0xFFFFFFFFu, k0, k1);
+                const T u1 = M::u(wd.x), u2 = M::u(wd.y);
                 const T dl = delta[m];
                 const T cth = T(1) - T(2) * u1;
                 const T sth = T(2) * M::sqrt_(u1 * (T(1) - u1));
@@ -285,7 +310,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
         }
         tries = wave_sum_u32(tries);
         if ((threadIdx.x & 63) == 0 && tries) atomicAdd(&a.tries_part[tile], (unsigned long long)tries);
-    });
+        if (!w.next()) break;
+        tile = w.tile();
+        tl = load_tile(a.tiles, tile);
+        d = load_desc(a.desc + tl.x);
+    }
 }
 
 // Over-relaxation substep (paper Sec. 2, over-relaxation equation, in its
@@ -823,59 +852,55 @@ static inline dim3 grid_of(const KArgs &a, int grid) {
     return dim3((unsigned)g);
 }
 
-template <class T, int MU, int NL, int W>
-static void launch_hb_w(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq) {
+// With timing events the launch itself stamps them with the kernel's own
+// start and end (the dispatch's timestamps), so nothing is queued between
+// the events and the kernel.
+template <class K>
+static void launch_ev(K kern, dim3 g, dim3 b, hipStream_t s, const Ev &ev, const KArgs &a, int par) {
+    if (ev.a && ev.b) hipExtLaunchKernelGGL(kern, g, b, 0, s, ev.a, ev.b, 0, a, par);
+    else hipLaunchKernelGGL(kern, g, b, 0, s, a, par);
+}
+
+template <class T, int MU, int NL>
+static void launch_hb_nl(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq,
+                         const Ev &ev) {
     const dim3 g = grid_of(a, grid), b(block);
     if (plaq) {
         if constexpr (MU >= 1) {
-            if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, true, W>), g, b, 0, s, a, par);
-            else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, true, W>), g, b, 0, s, a, par);
+            if (trace) launch_ev(k_heatbath<T, MU, true, NL, true>, g, b, s, ev, a, par);
+            else launch_ev(k_heatbath<T, MU, false, NL, true>, g, b, s, ev, a, par);
         }
     } else {
-        if (trace) hipLaunchKernelGGL((k_heatbath<T, MU, true, NL, false, W>), g, b, 0, s, a, par);
-        else hipLaunchKernelGGL((k_heatbath<T, MU, false, NL, false, W>), g, b, 0, s, a, par);
+        if (trace) launch_ev(k_heatbath<T, MU, true, NL, false>, g, b, s, ev, a, par);
+        else launch_ev(k_heatbath<T, MU, false, NL, false>, g, b, s, ev, a, par);
     }
-}
-
-// waves: 8 selects the binary32 build limited to 64 VGPRs (eight
-// wavefronts per SIMD); otherwise the compiler's register allocation.
-template <class T, int MU, int NL>
-static void launch_hb_nl(const KArgs &a, int par, int block, int grid, hipStream_t s, bool trace, bool plaq,
-                         int waves) {
-    if constexpr (sizeof(T) == 4) {
-        if (waves == 8 && !trace) {
-            launch_hb_w<T, MU, NL, 8>(a, par, block, grid, s, trace, plaq);
-            return;
-        }
-    }
-    launch_hb_w<T, MU, NL, 1>(a, par, block, grid, s, trace, plaq);
 }
 
 template <class T, int MU>
 static void launch_hb_mu(const KArgs &a, int par, int nl, int block, int grid, hipStream_t s, bool trace,
-                         bool plaq, int waves) {
+                         bool plaq, const Ev &ev) {
     switch (nl) {
-    case 1: launch_hb_nl<T, MU, 1>(a, par, block, grid, s, trace, plaq, waves); break;
-    case 2: launch_hb_nl<T, MU, 2>(a, par, block, grid, s, trace, plaq, waves); break;
-    default: launch_hb_nl<T, MU, 4>(a, par, block, grid, s, trace, plaq, waves); break;
+    case 1: launch_hb_nl<T, MU, 1>(a, par, block, grid, s, trace, plaq, ev); break;
+    case 2: launch_hb_nl<T, MU, 2>(a, par, block, grid, s, trace, plaq, ev); break;
+    default: launch_hb_nl<T, MU, 4>(a, par, block, grid, s, trace, plaq, ev); break;
     }
 }
 
 template <class T>
 static void launch_hb_t(const KArgs &a, int mu, int par, int nl, int block, int grid, hipStream_t s,
-                        bool trace, bool plaq, int waves) {
+                        bool trace, bool plaq, const Ev &ev) {
     switch (mu) {
-    case 0: launch_hb_mu<T, 0>(a, par, nl, block, grid, s, trace, false, waves); break;
-    case 1: launch_hb_mu<T, 1>(a, par, nl, block, grid, s, trace, plaq, waves); break;
-    case 2: launch_hb_mu<T, 2>(a, par, nl, block, grid, s, trace, plaq, waves); break;
-    default: launch_hb_mu<T, 3>(a, par, nl, block, grid, s, trace, plaq, waves); break;
+    case 0: launch_hb_mu<T, 0>(a, par, nl, block, grid, s, trace, false, ev); break;
+    case 1: launch_hb_mu<T, 1>(a, par, nl, block, grid, s, trace, plaq, ev); break;
+    case 2: launch_hb_mu<T, 2>(a, par, nl, block, grid, s, trace, plaq, ev); break;
+    default: launch_hb_mu<T, 3>(a, par, nl, block, grid, s, trace, plaq, ev); break;
     }
 }
 
 void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
-                     bool trace, bool plaq, int waves) {
-    if (f32) launch_hb_t<float>(a, mu, par, nl, block, grid, s, trace, plaq, waves);
-    else launch_hb_t<double>(a, mu, par, nl, block, grid, s, trace, plaq, waves);
+                     bool trace, bool plaq, const Ev &ev) {
+    if (f32) launch_hb_t<float>(a, mu, par, nl, block, grid, s, trace, plaq, ev);
+    else launch_hb_t<double>(a, mu, par, nl, block, grid, s, trace, plaq, ev);
 }
 
 template <class T>

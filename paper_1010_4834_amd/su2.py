@@ -63,8 +63,8 @@ _SIGS = {
     "su2_get_tries": (_I, [_P, _P]),
     "su2_save": (_I, [_P, C.c_char_p]),
     "su2_load": (_I, [C.c_char_p, _PP]),
-    "su2_set_launch": (_I, [_P, _I, _I, _I, _I, _I]),
-    "su2_get_launch": (_I, [_P, _P, _P, _P, _P, _P]),
+    "su2_set_launch": (_I, [_P, _I, _I, _I, _I]),
+    "su2_get_launch": (_I, [_P, _P, _P, _P, _P]),
     "su2_autotune": (_I, [_P, _D]),
     "su2_set_timing": (_I, [_P, _I]),
     "su2_get_timing": (_I, [_P, _I, _P, _P]),
@@ -76,8 +76,8 @@ _SIGS = {
     "su2_ensemble_get_links": (_I, [_P, _I, _P]),
     "su2_ensemble_set_links": (_I, [_P, _I, _P]),
     "su2_ensemble_stats": (_I, [_P, _P, _P]),
-    "su2_ensemble_set_launch": (_I, [_P, _I, _I, _I, _I, _I]),
-    "su2_ensemble_get_launch": (_I, [_P, _P, _P, _P, _P, _P]),
+    "su2_ensemble_set_launch": (_I, [_P, _I, _I, _I, _I]),
+    "su2_ensemble_get_launch": (_I, [_P, _P, _P, _P, _P]),
     "su2_ensemble_autotune": (_I, [_P]),
     "su2_ensemble_set_timing": (_I, [_P, _I]),
     "su2_ensemble_get_timing": (_I, [_P, _I, _P, _P]),
@@ -222,12 +222,12 @@ def su2_load(path):
     return h
 
 
-def su2_set_launch(h, block, grid, remap, links_per_lane=1, waves_per_simd=0):
-    _chk(_lib.su2_set_launch(h, block, grid, remap, links_per_lane, waves_per_simd), "su2_set_launch")
+def su2_set_launch(h, block, grid, remap, links_per_lane=1):
+    _chk(_lib.su2_set_launch(h, block, grid, remap, links_per_lane), "su2_set_launch")
 
 
 def su2_get_launch(h):
-    v = [C.c_int() for _ in range(5)]
+    v = [C.c_int() for _ in range(4)]
     _chk(_lib.su2_get_launch(h, *[C.byref(x) for x in v]), "su2_get_launch")
     return tuple(x.value for x in v)
 
@@ -293,13 +293,12 @@ def su2_ensemble_stats(h):
     return t.value, u.value
 
 
-def su2_ensemble_set_launch(h, block, grid, remap, links_per_lane=1, waves_per_simd=0):
-    _chk(_lib.su2_ensemble_set_launch(h, block, grid, remap, links_per_lane, waves_per_simd),
-         "su2_ensemble_set_launch")
+def su2_ensemble_set_launch(h, block, grid, remap, links_per_lane=1):
+    _chk(_lib.su2_ensemble_set_launch(h, block, grid, remap, links_per_lane), "su2_ensemble_set_launch")
 
 
 def su2_ensemble_get_launch(h):
-    v = [C.c_int() for _ in range(5)]
+    v = [C.c_int() for _ in range(4)]
     _chk(_lib.su2_ensemble_get_launch(h, *[C.byref(x) for x in v]), "su2_ensemble_get_launch")
     return tuple(x.value for x in v)
 

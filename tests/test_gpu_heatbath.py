@@ -180,7 +180,7 @@ def test_launch_shapes_bitwise(su2, orc):
     for block, grid, remap, nl in ((256, 0, 1, 1), (64, 0, 0, 2), (128, 16, 1, 4), (192, 8, 0, 1),
                                    (64, 24, 1, 4), (256, 0, 0, 2)):
         lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
-        su2.su2_set_launch(lat.h, block, grid, remap, nl, 0)
+        su2.su2_set_launch(lat.h, block, grid, remap, nl)
         lat.set_links(U)
         lat.heatbath(2.4, 3, 6)
         G = lat.get_links()
@@ -199,20 +199,21 @@ def test_launch_shapes_bitwise(su2, orc):
         del os.environ["SU2_NO_GRAPH"]
 
 
-def test_occupancy_variant_bitwise_fp32(su2):
-    """The binary32 heat bath built for 64 VGPRs gives the same links."""
+def test_launch_shapes_bitwise_fp32(su2):
+    """Binary32 links do not depend on the launch shape either."""
     dims = (8, 6, 4, 10)
     U = inputs.random_config(dims, 37).astype(np.float32).astype(np.float64)
     out = []
-    for waves in (0, 8):
+    for launch in ((256, 0, 1, 1), (128, 0, 1, 2), (64, 16, 0, 4), (192, 8, 1, 2)):
         lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F32)
-        su2.su2_set_launch(lat.h, 128, 0, 1, 2, waves)
-        assert su2.su2_get_launch(lat.h)[4] == waves
+        su2.su2_set_launch(lat.h, *launch)
+        assert su2.su2_get_launch(lat.h) == launch
         lat.set_links(U)
         lat.heatbath(2.5, 2, 3)
         out.append(lat.get_links())
         lat.close()
-    assert np.array_equal(out[0], out[1])
+    for G in out[1:]:
+        assert np.array_equal(G, out[0])
 
 
 def test_overrelax_fp64(su2, orc):
