@@ -13,7 +13,12 @@ stream it runs on), the plain FP64 single-lattice form on the same GPU for
 comparison, and the serial FP64 oracle timed on the host cores on a bounded
 sample.
 
-  python bench.py [--steps K] [--warmup W] [--config c2|control64|c3|c5]
+  python bench.py [--steps K] [--warmup W] [--config c2|control64|c3|c4|c5]
+
+The other configurations are side measurements of the same library: control64
+(a lattice larger than the Infinity Cache), c3 and c5 (ensembles; c5 also
+times the plain FP64 single-lattice form looped over its 64 lattices) and c4
+(24^3x48: heat bath, APE smearing and Wilson loops per configuration).
 """
 import argparse
 import json
@@ -62,6 +67,10 @@ def configs():
         "c5": dict(dims=c5[0], betas=c5[1], seed=5, poly=True,
                    desc="64 uneven lattices L^3xNt, L in {8,12,16,24}, Nt in {4,6,8,L}, "
                         "beta in [2.2,2.8], 1 sweep + plaquette + Polyakov per step"),
+        "c4": dict(dims=[(24, 24, 24, 48)], betas=[2.5], seed=4, poly=False,
+                   desc="24^3x48, beta=2.5: per configuration 5 heat-bath sweeps, APE smearing "
+                        "(alpha 0.7, 25 steps) of the spatial links and on-axis Wilson loops "
+                        "W(R<=12, T<=16)"),
     }
 
 
@@ -80,6 +89,97 @@ def cpu_baseline(dims, beta, seed, nsweeps):
     return 4 * V * nsweeps / dt, dt
 
 
+def copy_probe(torch):
+    """Device-to-device copy of 1 GiB: the achievable streaming bandwidth."""
+    x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        y.copy_(x)
+    c1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
+def bench_c4(su2, args, cfg, stream):
+    """Per configuration: 5 heat-bath sweeps, APE smearing, Wilson loops."""
+    import numpy as np
+    import torch
+    dims, beta, seed = cfg["dims"][0], cfg["betas"][0], cfg["seed"]
+    V = int(np.prod(dims))
+    nconf = max(2, args.steps // 20)
+    lat = su2.Lattice(dims, start=su2.HOT, seed=seed, prec=su2.F32, stream=stream.cuda_stream)
+    if args.launch:
+        su2.su2_set_launch(lat.h, *[int(x) for x in args.launch.split(",")])
+    elif not args.no_tune:
+        su2.su2_autotune(lat.h, beta)
+    lat.heatbath(beta, args.warmup, seed)
+
+    def one_config():
+        lat.heatbath(beta, 5, seed)
+        lat.ape_smear(0.7, 25)
+        return lat.wilson_loops(12, 16)
+
+    one_config()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nconf):
+        W = one_config()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    assert np.isfinite(W).all() and W[0] > 0
+    su2.su2_set_timing(lat.h, 1)
+    for _ in range(nconf):
+        one_config()
+    t = {k: su2.su2_get_timing(lat.h, getattr(su2, k)) for k in ("K_HEATBATH", "K_APE", "K_WILSON")}
+    su2.su2_set_timing(lat.h, 0)
+    lat.close()
+    ms = {k: v[0] / nconf for k, v in t.items()}
+    ape_step_us = 1e3 * t["K_APE"][0] / max(t["K_APE"][1], 1)
+    ape_bytes = 6 * V * 16   # 3V spatial links read, 3V written per step
+    return {
+        "metric": "APE smearing + Wilson loops time per configuration, 24^3x48",
+        "value": ms["K_APE"] + ms["K_WILSON"], "unit": "ms per configuration", "n_gpus": 1,
+        "steps": nconf, "warmup": args.warmup, "ms_per_step": 1e3 * secs / nconf,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (Philox hot start)",
+        "config": {"workload": cfg["desc"], "lattices": 1, "sites": V},
+        "kernel_ms_per_config": {"heatbath_5_sweeps": ms["K_HEATBATH"], "ape_25_steps": ms["K_APE"],
+                                 "wilson_R12_T16": ms["K_WILSON"]},
+        "ape_step": {"avg_launch_us": ape_step_us, "bytes_per_launch": ape_bytes,
+                     "GBs": ape_bytes / (ape_step_us * 1e-6) / 1e9},
+        "W_1_1": float(W[0]),
+    }
+
+
+def fp64_loop(su2, dims_list, betas, seed, nsteps):
+    """The plain FP64 single-lattice form looped over the lattices: per step
+    one heat-bath sweep + plaquette of each lattice in turn."""
+    import numpy as np
+    import torch
+    lats = [su2.Lattice(d, start=su2.HOT, seed=seed, prec=su2.F64) for d in dims_list]
+    for lat, b in zip(lats, betas):
+        lat.heatbath(b, 2, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        for lat, b in zip(lats, betas):
+            lat.heatbath(b, 1, seed)
+            lat.plaquette()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    for lat in lats:
+        lat.close()
+    upd = 4 * sum(int(np.prod(d)) for d in dims_list) * nsteps
+    return upd / secs, secs / nsteps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +190,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 1 GiB device copy (counter calibration)")
+                    help="run the 1 GiB device copy also for configurations other than c2")
+    ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--launch", default=None,
                     help="block,grid,xcd_remap,links_per_lane (skips tuning)")
@@ -111,6 +212,9 @@ def main():
     updates_per_step = 4 * V_tot
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.config == "c4":
+        print(json.dumps(bench_c4(su2, args, cfg, stream)), flush=True)
+        return
 
     ens = su2.su2_ensemble_create(dims, betas, su2.HOT, seed, su2.F32)
     su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
@@ -209,20 +313,14 @@ def main():
                              "hb_GBs": (updates_per_step // 8) * 256 / (hb64_us * 1e-6) / 1e9,
                              "speedup_fp32_batched": value / v64}
 
-    if args.copy_probe:
-        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record()
-        for _ in range(5):
-            y.copy_(x)
-        c1.record()
-        torch.cuda.synchronize()
-        out["copy_probe_GBs"] = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
-        del x, y
+    if not args.no_fp64 and n > 1:
+        v64, s64 = fp64_loop(su2, dims, betas, seed, max(5, args.steps // 20))
+        out["fp64_plain_loop"] = {"value": v64, "ms_per_step": 1e3 * s64,
+                                  "form": "plain FP64 single-lattice calls looped over the lattices",
+                                  "speedup_fp32_batched": value / v64}
+
+    if (args.config == "c2" or args.copy_probe) and not args.no_copy_probe:
+        out["copy_probe_GBs"] = copy_probe(torch)
 
     if not args.no_cpu_baseline and args.config == "c2":
         rate, dt = cpu_baseline(dims[0], betas[0], seed, args.cpu_sweeps)

@@ -1,0 +1,92 @@
+"""Static quark-antiquark potential from APE-smeared Wilson loops (paper
+Sec. 5: effective-mass ratio of W(R,T), Cornell fit, string tension and
+lattice spacing; table of sigma a^2 at beta = 2.5 and 2.8).
+
+Every lattice step runs in libsu2.so: heat-bath sweeps (optionally mixed
+with over-relaxation), APE smearing of the spatial links and the on-axis
+Wilson loops of each configuration.  The fit is host-side numerics
+(analysis.py).
+
+  python -m paper_1010_4834_amd.static_potential --nconf 2000
+"""
+import argparse
+import json
+import math
+
+import numpy as np
+
+from . import analysis
+
+# APE weight of the paper's table (w = 0.2 on each of the four spatial
+# staples, normalised by 1 + 4w) in the (1 - alpha) U + alpha/4 sum form.
+APE_W = 0.2
+APE_ALPHA = 4 * APE_W / (1 + 4 * APE_W)
+HBARC_MEV_FM = 197.0
+SQRT_SIGMA_MEV = 440.0
+
+
+def measure(dims=(24, 24, 24, 32), beta=2.5, seed=11, ntherm=200, nconf=200, nsep=5, overrelax=0,
+            ape_alpha=APE_ALPHA, ape_steps=25, rmax=10, tmax=12, prec=None, stream=None):
+    """W(R,T) of nconf configurations, nsep updates apart after ntherm
+    thermalisation updates; an update is one heat-bath sweep followed by
+    `overrelax` over-relaxation sweeps.  Returns [nconf, rmax, tmax]."""
+    from . import su2
+    prec = su2.F32 if prec is None else prec
+    lat = su2.Lattice(dims, start=su2.HOT, seed=seed, prec=prec, stream=stream)
+    try:
+        def update(n):
+            if overrelax == 0:
+                lat.heatbath(beta, n, seed)
+                return
+            for _ in range(n):
+                lat.heatbath(beta, 1, seed)
+                lat.overrelax(overrelax)
+
+        update(ntherm)
+        out = np.empty((nconf, rmax, tmax))
+        for c in range(nconf):
+            update(nsep)
+            lat.ape_smear(ape_alpha, ape_steps)
+            out[c] = np.asarray(lat.wilson_loops(rmax, tmax)).reshape(rmax, tmax)
+        return out
+    finally:
+        lat.close()
+
+
+def lattice_spacing_fm(sigma_a2):
+    """a from sigma a^2 with sqrt(sigma) = 440 MeV (paper Sec. 5)."""
+    return math.sqrt(sigma_a2) * HBARC_MEV_FM / SQRT_SIGMA_MEV
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--dims", default="24,24,24,32")
+    ap.add_argument("--beta", type=float, default=2.5)
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--ntherm", type=int, default=200)
+    ap.add_argument("--nconf", type=int, default=400)
+    ap.add_argument("--nsep", type=int, default=5)
+    ap.add_argument("--overrelax", type=int, default=0)
+    ap.add_argument("--ape-steps", type=int, default=25)
+    ap.add_argument("--ape-alpha", type=float, default=APE_ALPHA)
+    ap.add_argument("--rmax", type=int, default=10)
+    ap.add_argument("--tmax", type=int, default=12)
+    ap.add_argument("--t0", type=int, default=4)
+    ap.add_argument("--rmin-fit", type=int, default=2)
+    ap.add_argument("--rmax-fit", type=int, default=10)
+    ap.add_argument("--nbins", type=int, default=20)
+    ap.add_argument("--fp64", action="store_true")
+    args = ap.parse_args(argv)
+    from . import su2
+    dims = tuple(int(x) for x in args.dims.split(","))
+    W = measure(dims, args.beta, args.seed, args.ntherm, args.nconf, args.nsep, args.overrelax,
+                args.ape_alpha, args.ape_steps, args.rmax, args.tmax, su2.F64 if args.fp64 else su2.F32)
+    res = analysis.static_potential(W, args.t0, args.rmin_fit, args.rmax_fit, args.nbins)
+    res["a_fm"] = lattice_spacing_fm(res["sigma"]) if res["sigma"] > 0 else float("nan")
+    print(json.dumps({k: (v.tolist() if isinstance(v, np.ndarray) else float(v) if isinstance(v, np.floating)
+                          else v) for k, v in res.items()}))
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -33,6 +33,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "(python -c 'import __graft_entry__ as g; g.build()')")
 
+# torch ships its own HIP runtime under the same SONAME as the system one
+# libsu2.so is linked against.  Loading torch first makes libsu2.so bind to
+# that runtime, so the process holds a single HIP runtime whatever the
+# caller imports first (with two, the second one sees no device and device
+# pointers could not be shared with torch tensors).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 _P, _I, _D = C.c_void_p, C.c_int, C.c_double
 _U64, _U32, _SZ, _I64 = C.c_uint64, C.c_uint32, C.c_size_t, C.c_int64

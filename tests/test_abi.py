@@ -51,3 +51,16 @@ def test_no_device():
     with pytest.raises(su2.SU2Error) as e:
         su2.su2_create(8, 8, 8, 8, su2.COLD, 1, su2.F32)
     assert e.value.status == su2.ENODEV
+
+
+def test_single_hip_runtime():
+    """Importing the binding before torch still leaves one HIP runtime in the
+    process (torch's): two runtimes cannot share devices or pointers."""
+    import sys
+    code = ("from paper_1010_4834_amd import su2\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"

@@ -1,0 +1,87 @@
+"""Long-run agreement: beyond a few sweeps the chain is chaotic, so GPU and
+oracle runs are compared statistically.  Independent chains (different
+seeds) of the GPU path (binary32 and binary64 links) and of the oracle give
+the same mean plaquette and mean |Polyakov loop| within three standard
+deviations of the combined binned jackknife errors.
+
+Sizes are reduced stand-ins for the production workloads so that the
+serial oracle finishes in seconds: 10^4 at beta = 2.3 (plaquette) and
+8^3 x 4 at beta = 2.2 and 2.45 (either side of the Nt = 4 transition) for
+the Polyakov loop."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1010_4834_amd import analysis as an
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def su2():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1010_4834_amd import su2 as s
+    return s
+
+
+def oracle_series(orc, dims, beta, seed, nsweeps):
+    U = orc.hot(dims, seed)
+    P = np.empty(nsweeps)
+    L = np.empty(nsweeps)
+    for sw in range(nsweeps):
+        orc.heatbath_sweep(dims, U, beta, seed, sw)
+        P[sw] = orc.plaquette(dims, U)[0]
+        L[sw] = orc.polyakov(dims, U)
+    return P, L
+
+
+def gpu_series(su2, dims, beta, seed, nsweeps, prec):
+    ens = su2.Ensemble([dims], [beta], start=su2.HOT, seed=seed, prec=prec)
+    P, L = ens.run(nsweeps, seed)
+    ens.close()
+    return P[0], L[0]
+
+
+def mean_err(x, discard, nbins):
+    est, err, _ = an.jackknife(an.bin_series(np.asarray(x)[discard:], nbins))
+    return float(est), float(err)
+
+
+def agree(name, a, b):
+    (m1, e1), (m2, e2) = a, b
+    z = abs(m1 - m2) / np.hypot(e1, e2)
+    print(f"{name}: {m1:.6f}({e1:.6f}) vs {m2:.6f}({e2:.6f}), {z:.2f} sigma", flush=True)
+    assert z <= 3.0, name
+
+
+def test_plaquette_long_run(su2, orc):
+    dims, beta, n, discard, nbins = (10, 10, 10, 10), 2.3, 420, 60, 12
+    t0 = time.perf_counter()
+    Po, _ = oracle_series(orc, dims, beta, 101, n)
+    print(f"oracle {n} sweeps of {dims}: {time.perf_counter() - t0:.1f} s", flush=True)
+    ref = mean_err(Po, discard, nbins)
+    for prec, seed in (("F32", 202), ("F64", 303)):
+        Pg, _ = gpu_series(su2, dims, beta, seed, n, getattr(su2, prec))
+        agree(f"<P> {prec} GPU vs oracle", mean_err(Pg, discard, nbins), ref)
+    # a cross-check that the test can see a difference: a 0.5% shift of the
+    # coupling moves <P> by many sigma
+    Pb, _ = gpu_series(su2, dims, beta * 1.005, 404, n, su2.F32)
+    m, e = mean_err(Pb, discard, nbins)
+    assert abs(m - ref[0]) / np.hypot(e, ref[1]) > 3.0
+
+
+@pytest.mark.parametrize("beta", [2.2, 2.45])
+def test_polyakov_long_run(su2, orc, beta):
+    # near the transition |L| decorrelates slowly: long runs, long bins
+    dims, n, discard, nbins = (8, 8, 8, 4), 4000, 200, 16
+    t0 = time.perf_counter()
+    Po, Lo = oracle_series(orc, dims, beta, 111, n)
+    print(f"oracle {n} sweeps of {dims} at beta {beta}: {time.perf_counter() - t0:.1f} s", flush=True)
+    refP, refL = mean_err(Po, discard, nbins), mean_err(np.abs(Lo), discard, nbins)
+    Pg, Lg = gpu_series(su2, dims, beta, 222, n, su2.F32)
+    agree(f"<P> beta {beta}", mean_err(Pg, discard, nbins), refP)
+    agree(f"<|L|> beta {beta}", mean_err(np.abs(Lg), discard, nbins), refL)
+    sys.stdout.flush()
