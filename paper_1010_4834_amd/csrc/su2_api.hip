@@ -64,6 +64,7 @@ struct su2_ensemble_s {
     unsigned long long updates = 0;
 
     double *part_plaq = nullptr, *part_poly = nullptr, *part_hb = nullptr;
+    int nslots = 1;                 // per-sweep slots of part_hb / part_poly (series batches)
     unsigned *fin_cnt = nullptr;    // per-lattice arrival tickets of the final reduction
     double *fin_chunk = nullptr;    // per-workgroup chunk sums of the final reduction
     int fin_chunks = 1;             // workgroups per lattice in the final reduction
@@ -165,6 +166,8 @@ KArgs kargs(su2_ensemble_s *E, int which = 0) {
     a.tries_part = E->tries_part;
     a.plaq_part = E->part_hb;
     a.sampler = E->sampler;
+    a.advance = 0;
+    a.nslots = 0;
     return a;
 }
 
@@ -279,8 +282,13 @@ su2_status build_tiles(su2_ensemble_s *E) {
     CHK(dalloc(E, &E->mtiles, sizeof(Tile) * E->nmtiles));
     CHK(dalloc(E, &E->tries_part, sizeof(unsigned long long) * E->ntiles));
     CHK(dalloc(E, &E->part_plaq, sizeof(double) * 4 * E->ntiles));
-    CHK(dalloc(E, &E->part_poly, sizeof(double) * 2 * E->nstiles));
-    CHK(dalloc(E, &E->part_hb, sizeof(double) * 12 * E->nmtiles));
+    {   // series partials of up to nslots sweeps (about 64 MiB at most),
+        // reduced once per batch of sweeps
+        const size_t per_sweep = sizeof(double) * (12 * (size_t)E->nmtiles + 2 * (size_t)E->nstiles);
+        E->nslots = (int)std::min<size_t>(512, std::max<size_t>(1, (size_t(64) << 20) / per_sweep));
+    }
+    CHK(dalloc(E, &E->part_poly, sizeof(double) * 2 * (size_t)E->nstiles * E->nslots));
+    CHK(dalloc(E, &E->part_hb, sizeof(double) * 12 * (size_t)E->nmtiles * E->nslots));
     {   // final-reduction workgroups per lattice: ~2048 partial tiles each
         int most = 1;
         for (const LatDesc &d : E->hdesc) most = std::max(most, std::max(d.nmtile, std::max(d.ntile, d.nstile)));
@@ -289,7 +297,7 @@ su2_status build_tiles(su2_ensemble_s *E) {
     CHK(dalloc(E, &E->fin_cnt, sizeof(unsigned) * E->n));
     CHK(dalloc(E, &E->fin_chunk, sizeof(double) * 6 * (size_t)E->n * E->fin_chunks));
     HIPCHK(hipMemsetAsync(E->fin_cnt, 0, sizeof(unsigned) * E->n, E->stream()));
-    HIPCHK(hipMemsetAsync(E->part_hb, 0, sizeof(double) * 12 * E->nmtiles, E->stream()));
+    HIPCHK(hipMemsetAsync(E->part_hb, 0, sizeof(double) * 12 * (size_t)E->nmtiles * E->nslots, E->stream()));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, E->stream()));
     HIPCHK(hipMemcpyAsync(E->tiles, E->htiles.data(), sizeof(Tile) * E->ntiles, hipMemcpyHostToDevice,
                           E->stream()));
@@ -307,6 +315,7 @@ su2_status build_tiles(su2_ensemble_s *E) {
 
 // upload seed / sweep / run_base (not the device-written error word)
 su2_status upload_state(su2_ensemble_s *E) {
+    E->hst.next = E->hst.sweep;
     HIPCHK(hipMemcpyAsync(E->st, &E->hst, offsetof(DevState, err), hipMemcpyHostToDevice, E->stream()));
     HIPCHK(hipStreamSynchronize(E->stream()));
     return SU2_OK;
@@ -409,10 +418,15 @@ void destroy_common(su2_ensemble_s *E) {
 }
 
 // ---- one sweep --------------------------------------------------------------
+// Eight substep launches that also advance the device sweep counter; with a
+// plaquette series the odd substeps mu >= 1 sum the plaquettes of the
+// sweep's final configuration into the sweep's partial slot, with a
+// Polyakov series k_polyakov does the same.  The slots are reduced per
+// batch of sweeps (series_batch), so a sweep holds no reduction launch.
 su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
-    const KArgs a = kargs(E, 3);
-    // with a plaquette series the odd substeps mu >= 1 also sum the
-    // plaquettes of the sweep's final configuration (no separate pass)
+    KArgs a = kargs(E, 3);
+    a.advance = 1;
+    a.nslots = E->nslots;
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
@@ -422,20 +436,24 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
             t.done(s);
         }
     if (meas & 2) {
+        KArgs p = kargs(E, 1);
+        p.nslots = E->nslots;
         Timed t(E, SU2_K_POLYAKOV, s);
-        su2::launch_polyakov(kargs(E, 1), E->f32, E->part_poly, E->block, E->grid, s);
+        su2::launch_polyakov(p, E->f32, E->part_poly, E->block, E->grid, s);
         t.done(s);
     }
-    if (meas) {
-        // per-lattice series values; the last block advances the sweep counter
-        Timed r(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, (meas & 1) ? E->part_hb : nullptr, 1,
-                             (meas & 2) ? E->part_poly : nullptr, E->st, E->fin_cnt, E->fin_chunk, 1, 1,
-                             E->ser_plaq, E->ser_poly, E->ser_cap, s);
-        r.done(s);
-    } else {
-        su2::launch_bump(E->st, s);
-    }
+    HIPCHK(hipGetLastError());
+    return SU2_OK;
+}
+
+// Series values of the nsw sweeps that started at host sweep index `first`.
+su2_status series_batch(su2_ensemble_s *E, int meas, unsigned first, int nsw, hipStream_t s) {
+    const unsigned k0 = first - E->hst.run_base;
+    Timed r(E, SU2_K_REDUCE, s);
+    su2::launch_series(E->ddesc, E->n, (meas & 1) ? E->part_hb : nullptr, 12 * (long long)E->nmtiles,
+                       (meas & 2) ? E->part_poly : nullptr, 2 * (long long)E->nstiles, (int)(k0 % E->nslots),
+                       E->nslots, nsw, E->ser_plaq, E->ser_poly, E->ser_cap, (int)k0, s);
+    r.done(s);
     HIPCHK(hipGetLastError());
     return SU2_OK;
 }
@@ -443,22 +461,27 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
 su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas) {
     hipStream_t s = E->stream();
     const bool use_graph = !E->timing && nsweeps > 1 && !std::getenv("SU2_NO_GRAPH");
-    if (use_graph) {
-        if (!E->gexec[meas]) {
-            hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
-            su2_status st = enqueue_sweep(E, meas, E->own);
-            hipGraph_t gg = nullptr;
-            hipError_t e = hipStreamEndCapture(E->own, &gg);
-            if (st != SU2_OK) return st;
-            HIPCHK(e);
-            g = gg;
-            HIPCHK(hipGraphInstantiate(&E->gexec[meas], g, nullptr, nullptr, 0));
-            HIPCHK(hipGraphDestroy(g));
+    if (use_graph && !E->gexec[meas]) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
+        su2_status st = enqueue_sweep(E, meas, E->own);
+        hipGraph_t gg = nullptr;
+        hipError_t e = hipStreamEndCapture(E->own, &gg);
+        if (st != SU2_OK) return st;
+        HIPCHK(e);
+        g = gg;
+        HIPCHK(hipGraphInstantiate(&E->gexec[meas], g, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(g));
+    }
+    // batches of at most nslots sweeps between series reductions
+    const int batch = meas ? E->nslots : nsweeps;
+    for (int done = 0; done < nsweeps; done += batch) {
+        const int b = std::min(batch, nsweeps - done);
+        for (int k = 0; k < b; ++k) {
+            if (use_graph) HIPCHK(hipGraphLaunch(E->gexec[meas], s));
+            else CHK(enqueue_sweep(E, meas, s));
         }
-        for (int k = 0; k < nsweeps; ++k) HIPCHK(hipGraphLaunch(E->gexec[meas], s));
-    } else {
-        for (int k = 0; k < nsweeps; ++k) CHK(enqueue_sweep(E, meas, s));
+        if (meas) CHK(series_batch(E, meas, E->hst.sweep + (unsigned)done, b, s));
     }
     E->hst.sweep += (unsigned)nsweeps;
     E->updates += (unsigned long long)nsweeps * (unsigned long long)E->total_links;
@@ -496,8 +519,8 @@ su2_status measure_plaquette(su2_ensemble_s *E, int l, double *avg, double *sp, 
     }
     {
         Timed t(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, E->part_plaq, 0, nullptr, E->st, E->fin_cnt,
-                             E->fin_chunk, 0, 0, E->res, nullptr, 4, s);
+        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, E->part_plaq, nullptr, E->fin_cnt, E->fin_chunk,
+                             E->res, nullptr, 4, s);
         t.done(s);
     }
     HIPCHK(hipGetLastError());
@@ -519,8 +542,8 @@ su2_status measure_polyakov(su2_ensemble_s *E, int l, double *out) {
     }
     {
         Timed t(E, SU2_K_REDUCE, s);
-        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, nullptr, 0, E->part_poly, E->st, E->fin_cnt,
-                             E->fin_chunk, 0, 0, nullptr, E->res, 4, s);
+        su2::launch_finalize(E->ddesc, E->n, E->fin_chunks, nullptr, E->part_poly, E->fin_cnt, E->fin_chunk,
+                             nullptr, E->res, 4, s);
         t.done(s);
     }
     HIPCHK(hipGetLastError());

@@ -39,12 +39,17 @@ struct LatDesc {
 
 // Mutable state read by the kernels; lives in device memory so that one
 // captured graph serves every sweep.
+// The sweep counter advances without a kernel of its own: within a sweep the
+// first substep (mu = 0, even) reads `next` and publishes it as `sweep`, the
+// other substeps read `sweep`, and the last (mu = 3, odd) writes
+// `next = sweep + 1`.  Every workgroup writes the same value and no launch
+// reads a word that it writes, so one captured sweep serves every sweep.
 struct DevState {
     unsigned long long seed;
     unsigned int sweep;     // Philox sweep word of the sweep in progress
+    unsigned int next;      // sweep word of the following sweep
     unsigned int run_base;  // sweep index of the first sweep of a series
     unsigned int err;       // sampler try-cap hits (non-finite input)
-    unsigned int done;      // arrival ticket of the per-sweep final reduction
 };
 
 // A tile: lattice index and first index (half-site, spatial site or site).
@@ -232,6 +237,41 @@ __device__ __forceinline__ DD dd_add(DD a, DD b) {
     e += a.lo + b.lo;
     double h = s + e;
     return DD{h, e - (h - s)};
+}
+
+// Wavefront sums that need no lane-index registers: XOR butterflies within
+// each 32-lane half by ds_swizzle in bit-mask mode (lane j reads lane j ^ X),
+// then the two half sums read back as uniform values.  All 64 lanes must be
+// active; every lane receives the total.
+template <int X> __device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (X << 10));
+}
+template <int X> __device__ __forceinline__ double swz_xor(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const uint32_t lo = swz_xor<X>((uint32_t)b), hi = swz_xor<X>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
+    t += swz_xor<1>(t);
+    t += swz_xor<2>(t);
+    t += swz_xor<4>(t);
+    t += swz_xor<8>(t);
+    t += swz_xor<16>(t);
+    return (uint32_t)__builtin_amdgcn_readlane((int)t, 0) + (uint32_t)__builtin_amdgcn_readlane((int)t, 32);
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += swz_xor<1>(v);
+    v += swz_xor<2>(v);
+    v += swz_xor<4>(v);
+    v += swz_xor<8>(v);
+    v += swz_xor<16>(v);
+    return readlane_f64(v, 0) + readlane_f64(v, 32);
 }
 
 __device__ __forceinline__ DD dd_wave_sum(DD v) {

@@ -13,12 +13,14 @@ struct KArgs {
     int ntiles;
     int xcd_remap;
     void *links;                         // native link buffer
-    const DevState *st;                  // seed / sweep counter
+    DevState *st;                        // seed / sweep counter
     unsigned int *err;                   // sampler try-cap hits (&st->err)
     uint32_t *trace;                     // per-link try record or null
     unsigned long long *tries_part;      // per-tile try counts
-    double *plaq_part;                   // per-tile plaquette sums of the sweep
+    double *plaq_part;                   // per-sweep-slot tile plaquette sums
     int sampler;                         // 0 hybrid, 1 Creutz
+    int advance;                         // heat bath: substeps of whole sweeps (advance the counter)
+    int nslots;                          // series slots of the partial buffers (0: no series)
 };
 
 // Optional timing events stamped by the launch itself (both null: none).
@@ -35,17 +37,26 @@ void launch_to_canon(const KArgs &a, bool f32, const void *src, int ndir, double
                      hipStream_t s);
 void launch_unit_defect(const KArgs &a, bool f32, unsigned long long *out, int block, hipStream_t s);
 void launch_plaquette(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
+// Polyakov partials: one (hi, lo) pair per spatial tile; with a.nslots > 0
+// they go to series slot (sweep - run_base) % nslots (2 * ntiles doubles
+// per slot).
 void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid, hipStream_t s);
-// Final reduction of plaquette / Polyakov partials: `chunks` workgroups
-// per lattice, cnt[nlat] arrival tickets (zero between launches), chunk
-// scratch of 6 doubles per workgroup.
-// pp: plaquette partials of k_plaquette (4 per tile) or, with pp_hb, of
-// the heat-bath substeps (3 slots x 4 wavefronts per heat-bath tile,
-// unused wavefront entries zero); pl: Polyakov partials.
-void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp, int pp_hb, const double *pl,
-                     DevState *st, unsigned *cnt, double *chunk, int series, int bump, double *outp, double *outl,
-                     long long ostride, hipStream_t s);
-void launch_bump(DevState *st, hipStream_t s);
+// Final reduction of the standalone measurements: `chunks` workgroups per
+// lattice, cnt[nlat] arrival tickets (zero between launches), chunk scratch
+// of 6 doubles per workgroup.  pp: k_plaquette partials (4 per tile) ->
+// outp[l * ostride + 0..2] = (avg, spatial, temporal); pl: Polyakov
+// partials -> outl[l * ostride].
+void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp, const double *pl,
+                     unsigned *cnt, double *chunk, double *outp, double *outl, long long ostride, hipStream_t s);
+// Series values of nsw consecutive sweeps, slots slot0 .. slot0 + nsw - 1
+// (mod nslots): plaquette from the heat-bath partials (12 doubles per
+// heat-bath tile per slot: 3 planes x 4 wavefronts, unused entries zero;
+// slot stride pp_stride doubles) and Polyakov loop from the Polyakov
+// partials (slot stride pl_stride); either may be null.  Writes
+// outp / outl[l * ostride + out0 + j] for sweep j of the batch.
+void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp_stride, const double *pl,
+                   long long pl_stride, int slot0, int nslots, int nsw, double *outp, double *outl,
+                   long long ostride, int out0, hipStream_t s);
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s);
 void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,

@@ -114,8 +114,10 @@ __device__ __forceinline__ void gather(const LatDesc &d, const Blocks<T, 4> &B, 
     }
 }
 
-// Vlow (fused plaquette): the staples of the planes (nu, MU), nu < MU, are
-// also summed apart.
+// V accumulates nu ascending, upper then lower staple, in one chain of
+// fused multiply-adds.  The planes nu < MU come first, so Vlow (the fused
+// plaquette) is V as it stands after plane MU - 1: the substep updates its
+// links bit for bit the same with and without the plaquette.
 template <class T, int MU>
 __device__ __forceinline__ Q<T> combine(const Q<T> (&L)[18], Q<T> *Vlow = nullptr) {
     Q<T> V{T(0), T(0), T(0), T(0)};
@@ -124,16 +126,9 @@ __device__ __forceinline__ Q<T> combine(const Q<T> (&L)[18], Q<T> *Vlow = nullpt
         if (nu == MU) continue;
         const int q = 6 * (nu < MU ? nu : nu - 1);
         const Q<T> &A = L[q + 0], &Bm = L[q + 1], &C = L[q + 2], &D = L[q + 3], &E = L[q + 4], &F = L[q + 5];
-        if (Vlow && nu < MU) {
-            Q<T> P{T(0), T(0), T(0), T(0)};
-            qmul_acc(P, A, qdag(qmul(C, Bm)));
-            qmul_acc(P, qdag(qmul(E, D)), F);
-            qacc(*Vlow, P);
-            qacc(V, P);
-        } else {
-            qmul_acc(V, A, qdag(qmul(C, Bm)));
-            qmul_acc(V, qdag(qmul(E, D)), F);
-        }
+        qmul_acc(V, A, qdag(qmul(C, Bm)));
+        qmul_acc(V, qdag(qmul(E, D)), F);
+        if (Vlow && nu == MU - 1) *Vlow = V;
     }
     return V;
 }
@@ -158,11 +153,6 @@ template <class T, int N> __device__ __forceinline__ void put(T (&a)[N], int m, 
         if (m == k) a[k] = v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
-    return t;
-}
 
 // ---------------------------------------------------------------------------
 // Heat-bath substep (paper Sec. 2 heat bath; Sec. 4 chessboard): every link
@@ -189,8 +179,18 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
 template <class T, int MU, bool TRACE, int NL, bool PLAQ>
 __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
     using M = Mth<T>;
-    const uint32_t sweep = uni(a.st->sweep);
+    // the first substep of a sweep takes the sweep word from `next`, and so
+    // does a lone substep (no advance: part of the next sweep to run)
+    const bool first = a.advance && MU == 0 && par == 0;
+    const uint32_t sweep = uni((first || !a.advance) ? a.st->next : a.st->sweep);
     const uint32_t k0 = uni((unsigned)a.st->seed), k1 = uni((unsigned)(a.st->seed >> 32));
+    if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (first) a.st->sweep = sweep;
+        if (MU == 3 && par == 1) a.st->next = sweep + 1u;
+    }
+    double *plaq_part = a.plaq_part;
+    if (PLAQ && a.nslots > 0)
+        plaq_part += (long long)((sweep - uni(a.st->run_base)) % (uint32_t)a.nslots) * 12 * a.ntiles;
     TileWalk w(a.ntiles, a.xcd_remap);
     if (!w.ok()) return;
     int tile = w.tile();
@@ -303,10 +303,9 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             }
         }
         if (PLAQ) {
-#pragma unroll
-            for (int k = 32; k >= 1; k >>= 1) pq += __shfl_xor(pq, k, 64);
+            pq = wave_sum_f64(pq);
             if ((threadIdx.x & 63) == 0)
-                a.plaq_part[(3 * (long long)tile + (MU - 1)) * 4 + (threadIdx.x >> 6)] = pq;
+                plaq_part[(3 * (long long)tile + (MU - 1)) * 4 + (threadIdx.x >> 6)] = pq;
         }
         tries = wave_sum_u32(tries);
         if ((threadIdx.x & 63) == 0 && tries) atomicAdd(&a.tries_part[tile], (unsigned long long)tries);
@@ -500,6 +499,8 @@ __global__ __launch_bounds__(256) void k_plaquette(KArgs a, double *part) {
 template <class T>
 __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
     __shared__ DD lds[4];
+    if (a.nslots > 0)
+        part += (long long)((uni(a.st->sweep) - uni(a.st->run_base)) % (uint32_t)a.nslots) * 2 * a.ntiles;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tl = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tl.x);
@@ -526,32 +527,25 @@ __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
     });
 }
 
-// Final per-lattice reduction of tile partials in a fixed order.
-// Workgroup b handles chunk b % C of lattice b / C: it sums its share of
-// the lattice's tile partials, writes a (hi, lo) pair per quantity to
-// `chunk`, and the last chunk of the lattice to arrive (ticket in cnt[l])
-// combines the C pairs in chunk order and writes the result:
-//   plaquette (avg, spatial, temporal) or its series value, Polyakov loop.
-// series: slot (sweep - run_base) of out[l * ostride + slot]; with `bump`,
-// the last lattice to finish advances the sweep counter.
-// Plaquette partials: k_plaquette's (spatial, temporal) pairs per tile, or
-// with pp_hb the heat-bath substeps' [tile][slot 0,1 spatial, 2 temporal]
-// [wavefront] binary64 sums.  Polyakov partials: one pair per spatial tile.
+// Final per-lattice reduction of the standalone measurements' tile
+// partials in a fixed order.  Workgroup b handles chunk b % C of lattice
+// b / C: it sums its share of the lattice's partials, writes a (hi, lo) pair
+// per quantity to `chunk`, and the last chunk of the lattice to arrive
+// (ticket in cnt[l]) combines the C pairs in chunk order and writes the
+// plaquette (avg, spatial, temporal) and / or the Polyakov loop.
 __device__ __forceinline__ void chunk_range(int n, int C, int c, int &lo, int &hi) {
     lo = (int)(((long long)n * c) / C);
     hi = (int)(((long long)n * (c + 1)) / C);
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const double *pp, int pp_hb,
-                                                  const double *pl, DevState *st, unsigned *cnt, double *chunk,
-                                                  int C, int series, int bump, double *outp, double *outl,
+__global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const double *pp, const double *pl,
+                                                  unsigned *cnt, double *chunk, int C, double *outp, double *outl,
                                                   long long ostride) {
     __shared__ DD lds[3 * 4];
     __shared__ int last;
     last = 1;
     const int l = blockIdx.x / C, c = blockIdx.x % C;
     const LatDesc d = load_desc(desc + l);
-    const unsigned sweep = uni(st->sweep);
     // four independent compensated accumulators per quantity (the sums are
     // latency bound), combined in a fixed order
     DD a4[4][3];
@@ -559,29 +553,7 @@ __global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const dou
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int k = 0; k < 3; ++k) a4[u][k] = DD{0.0, 0.0};
-    if (pp && pp_hb) {
-        int lo, hi;
-        chunk_range(d.nmtile, C, c, lo, hi);
-        const double4 *q4 = reinterpret_cast<const double4 *>(pp) + 3 * (long long)d.mtile0;
-        for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
-            double4 v[4][3];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = t0 + u * (int)blockDim.x;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    v[u][k] = t < hi ? q4[3 * (long long)t + k] : make_double4(0.0, 0.0, 0.0, 0.0);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    DD &x = a4[u][k == 2 ? 1 : 0];
-                    x = dd_add(x, DD{(v[u][k].x + v[u][k].y), 0.0});
-                    x = dd_add(x, DD{(v[u][k].z + v[u][k].w), 0.0});
-                }
-        }
-    } else if (pp) {
+    if (pp) {
         int lo, hi;
         chunk_range(d.ntile, C, c, lo, hi);
         for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
@@ -638,38 +610,77 @@ __global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const dou
                     tot[k] = dd_add(tot[k], DD{ch[6 * cc + 2 * k], ch[6 * cc + 2 * k + 1]});
             cnt[l] = 0u;
         }
-        const long long idx = series ? (long long)(sweep - uni(st->run_base)) : 0;
         const double V = 2.0 * (double)d.vh;
         const double sp = tot[0].hi + tot[0].lo, tp = tot[1].hi + tot[1].lo;
         if (pp) {
-            if (series) {
-                outp[l * ostride + idx] = (sp + tp) / (6.0 * V);
-            } else {
-                double *o = outp + l * ostride;
-                o[0] = (sp + tp) / (6.0 * V);
-                o[1] = sp / (3.0 * V);
-                o[2] = tp / (3.0 * V);
-            }
+            double *o = outp + l * ostride;
+            o[0] = (sp + tp) / (6.0 * V);
+            o[1] = sp / (3.0 * V);
+            o[2] = tp / (3.0 * V);
         }
-        if (pl) outl[l * ostride + idx] = (tot[2].hi + tot[2].lo) / (double)d.ns;
-        if (bump) {
-            const unsigned nlat = gridDim.x / C;
-            if (nlat == 1) {
-                st->sweep = sweep + 1u;
-            } else {
-                __threadfence();
-                const unsigned ticket = atomicAdd(&st->done, 1u);
-                if (ticket == nlat - 1) {
-                    st->done = 0u;
-                    st->sweep = sweep + 1u;
-                }
-            }
-        }
+        if (pl) outl[l * ostride] = (tot[2].hi + tot[2].lo) / (double)d.ns;
     }
 }
 
-__global__ void k_bump(DevState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->sweep = st->sweep + 1u;
+// Series values of a batch of sweeps: workgroup (l, j) sums lattice l's
+// partials of slot (slot0 + j) % nslots in a fixed order -- the heat-bath
+// plaquette partials [tile][plane slot 0, 1 spatial, 2 temporal][wavefront]
+// and the Polyakov (hi, lo) pairs -- and writes the mean plaquette and
+// Polyakov loop of sweep out0 + j.
+__global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const double *pp, long long pp_stride,
+                                                const double *pl, long long pl_stride, int slot0, int nslots,
+                                                double *outp, double *outl, long long ostride, int out0) {
+    __shared__ DD lds[3 * 4];
+    const int l = blockIdx.x, j = blockIdx.y;
+    const long long slot = (slot0 + j) % nslots;
+    const LatDesc d = load_desc(desc + l);
+    DD a4[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a4[u][k] = DD{0.0, 0.0};
+    if (pp) {
+        const double4 *q4 = reinterpret_cast<const double4 *>(pp + slot * pp_stride) + 3 * (long long)d.mtile0;
+        const int n = d.nmtile;
+        for (int t0 = (int)threadIdx.x; t0 < n; t0 += 4 * blockDim.x) {
+            double4 v[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    v[u][k] = t < n ? q4[3 * (long long)t + k] : make_double4(0.0, 0.0, 0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    DD &x = a4[u][k == 2 ? 1 : 0];
+                    x = dd_add(x, DD{(v[u][k].x + v[u][k].y), 0.0});
+                    x = dd_add(x, DD{(v[u][k].z + v[u][k].w), 0.0});
+                }
+        }
+    }
+    if (pl) {
+        const double2 *q2 = reinterpret_cast<const double2 *>(pl + slot * pl_stride) + d.stile0;
+        const int n = d.nstile;
+        for (int t0 = (int)threadIdx.x; t0 < n; t0 += 4 * blockDim.x) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                if (t < n) a4[u][2] = dd_add(a4[u][2], DD{q2[t].x, q2[t].y});
+            }
+        }
+    }
+    DD acc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] = dd_add(dd_add(a4[0][k], a4[1][k]), dd_add(a4[2][k], a4[3][k]));
+    dd_block_sum<3>(acc, lds);
+    if (threadIdx.x == 0) {
+        const long long o = l * ostride + out0 + j;
+        if (pp) outp[o] = ((acc[0].hi + acc[0].lo) + (acc[1].hi + acc[1].lo)) / (12.0 * (double)d.vh);
+        if (pl) outl[o] = (acc[2].hi + acc[2].lo) / (double)d.ns;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -949,14 +960,19 @@ void launch_polyakov(const KArgs &a, bool f32, double *part, int block, int grid
     else hipLaunchKernelGGL((k_polyakov<double>), grid_of(a, grid), dim3(block), 0, s, a, part);
 }
 
-void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp, int pp_hb, const double *pl,
-                     DevState *st, unsigned *cnt, double *chunk, int series, int bump, double *outp, double *outl,
-                     long long ostride, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)(nlat * chunks)), dim3(256), 0, s, desc, pp, pp_hb, pl, st, cnt,
-                       chunk, chunks, series, bump, outp, outl, ostride);
+void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp, const double *pl,
+                     unsigned *cnt, double *chunk, double *outp, double *outl, long long ostride, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)(nlat * chunks)), dim3(256), 0, s, desc, pp, pl, cnt, chunk,
+                       chunks, outp, outl, ostride);
 }
 
-void launch_bump(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, st); }
+void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp_stride, const double *pl,
+                   long long pl_stride, int slot0, int nslots, int nsw, double *outp, double *outl,
+                   long long ostride, int out0, hipStream_t s) {
+    hipLaunchKernelGGL(k_series, dim3((unsigned)nlat, (unsigned)nsw), dim3(256), 0, s, desc, pp, pp_stride, pl,
+                       pl_stride, slot0, nslots, outp, outl, ostride, out0);
+}
+
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s) {

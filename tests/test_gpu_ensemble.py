@@ -70,3 +70,39 @@ def test_fused_plaquette_matches_standalone(su2, prec, tol):
             assert abs(P[i, 0] - lat.plaquette()[0]) < tol, (launch, i)
             lat.close()
     ens.close()
+
+
+def test_series_across_batches(su2):
+    """A run longer than the series slots of a large lattice (64^4: about
+    21 sweeps of partials) is reduced in several batches; every series value
+    equals the standalone plaquette of an identical lattice advanced one
+    sweep at a time."""
+    dims, beta, seed, n = (64, 64, 64, 64), 2.5, 9, 25
+    ens = su2.Ensemble([dims], [beta], start=su2.HOT, seed=seed, prec=su2.F32)
+    P, _ = ens.run(n, seed, plaq=True, poly=False)
+    ens.close()
+    lat = su2.Lattice(dims, start=su2.HOT, seed=seed, prec=su2.F32)
+    worst = 0.0
+    for k in range(n):
+        lat.heatbath(beta, 1, seed)
+        worst = max(worst, abs(P[0, k] - lat.plaquette()[0]))
+    lat.close()
+    print(f"64^4 series over batches: worst |dP| {worst:.2e}")
+    # same chain bit for bit; the two plaquette sums differ only in the
+    # binary32 rounding of ~1e8 terms of random sign
+    assert worst < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["F32", "F64"])
+def test_measuring_does_not_change_the_chain(su2, prec):
+    """Sweeps with the fused plaquette and Polyakov series leave the same
+    links, bit for bit, as sweeps without measurements."""
+    dims, beta, seed = (8, 6, 4, 10), 2.4, 13
+    p = getattr(su2, prec)
+    a = su2.Ensemble([dims], [beta], start=su2.HOT, seed=seed, prec=p)
+    a.run(6, seed, plaq=True, poly=True)
+    b = su2.Lattice(dims, start=su2.HOT, seed=seed, prec=p)
+    b.heatbath(beta, 6, seed)
+    assert np.array_equal(a.get_links(0), b.get_links())
+    a.close()
+    b.close()
