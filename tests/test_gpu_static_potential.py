@@ -1,0 +1,42 @@
+"""String tension at beta = 2.5 against the paper's table (Sec. 5; values
+in tests/golden/string_tension_table.txt).  Every lattice step runs in the
+library; the effective-mass ratio and the Cornell fit are host numerics.
+
+The paper prints neither its fit ranges nor its thermalisation, so this is
+a loose physics pin: the measured sigma a^2 must lie within three combined
+standard errors (ours and the paper's) of the printed value."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "string_tension_table.txt")
+
+
+def table():
+    rows = []
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            rows.append(dict(beta=float(f[0]), sigma=float(f[1]), dsigma=float(f[2]), a_fm=float(f[3]),
+                             dims=tuple(int(x) for x in f[5:9]), ape_w=float(f[9]), ape_n=int(f[10]),
+                             nconf=int(f[11])))
+    return rows
+
+
+def test_string_tension_beta_2_5():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1010_4834_amd import analysis, static_potential as sp
+    ref = [r for r in table() if r["beta"] == 2.5][0]
+    alpha = 4 * ref["ape_w"] / (1 + 4 * ref["ape_w"])
+    W = sp.measure(ref["dims"], ref["beta"], seed=11, ntherm=200, nconf=2000, nsep=5, ape_alpha=alpha,
+                   ape_steps=ref["ape_n"], rmax=12, tmax=12)
+    res = analysis.static_potential(W, t0=4, rmin=2, rmax=10, nbins=20)
+    z = abs(res["sigma"] - ref["sigma"]) / np.hypot(res["dsigma"], ref["dsigma"])
+    print(f"sigma a^2 = {res['sigma']:.5f}({res['dsigma']:.5f}) vs paper {ref['sigma']:.6f}({ref['dsigma']:.6f}):"
+          f" {z:.2f} sigma; a = {sp.lattice_spacing_fm(res['sigma']):.4f} fm")
+    assert np.all(np.diff(res["V"]) > 0)
+    assert z <= 3.0
