@@ -312,11 +312,16 @@ __device__ __forceinline__ unsigned uni(unsigned v) {
     return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Descriptor and tile tables are read-only while a kernel runs and are
+// indexed uniformly, so they are read through the constant address space:
+// scalar loads into scalar registers, no vector load and read-back.
+template <class T> using cptr = const __attribute__((address_space(4))) T *;
+
 // Descriptor of one lattice in scalar registers.
 __device__ __forceinline__ LatDesc load_desc(const LatDesc *p) {
     static_assert(sizeof(LatDesc) % 4 == 0, "descriptor is a whole number of dwords");
     LatDesc d;
-    const int *src = reinterpret_cast<const int *>(p);
+    const cptr<int> src = (cptr<int>)p;
     int *dst = reinterpret_cast<int *>(&d);
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(LatDesc) / 4); ++i) dst[i] = uni(src[i]);
@@ -324,8 +329,8 @@ __device__ __forceinline__ LatDesc load_desc(const LatDesc *p) {
 }
 
 __device__ __forceinline__ Tile load_tile(const Tile *t, int i) {
-    const Tile v = t[i];
-    return make_int2(uni(v.x), uni(v.y));
+    const cptr<int> p = (cptr<int>)(t + i);
+    return make_int2(uni(p[0]), uni(p[1]));
 }
 
 // ---------------------------------------------------------------------------
