@@ -162,6 +162,11 @@ template <> struct Links<double> {
 };
 
 // ---------------------------------------------------------------------------
+// a ^ b ^ c in one gfx950 three-input bit operation (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return (uint32_t)__builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 products on counter words 0 and 2 with a Weyl-advanced key.
 __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -174,8 +179,8 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         }
         const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -199,10 +204,14 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float ln(float x) {
         return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
     }
+    // lg: the cheapest logarithm (log2 here); ln(x) = LN_LG * lg(x)
+    static __device__ __forceinline__ float lg(float x) { return __builtin_amdgcn_logf(x); }
+    static constexpr float LN_LG = 0.693147180559945309f;
     static __device__ __forceinline__ float cos2pi(float r) { return __builtin_amdgcn_cosf(r); }
     static __device__ __forceinline__ float sin2pi(float r) { return __builtin_amdgcn_sinf(r); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
     static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
     static __device__ __forceinline__ float nan_() { return __builtin_nanf(""); }
@@ -212,6 +221,8 @@ template <> struct Mth<double> {
     // (2w+1) 2^-33 = w 2^-32 + 2^-33, exact
     static __device__ __forceinline__ double u(uint32_t w) { return fma((double)w, 0x1p-32, 0x1p-33); }
     static __device__ __forceinline__ double ln(double x) { return log(x); }
+    static __device__ __forceinline__ double lg(double x) { return log(x); }
+    static constexpr double LN_LG = 1.0;
     static __device__ __forceinline__ double cos2pi(double r) {
         return cos(6.283185307179586476925286766559 * r);
     }
@@ -220,6 +231,7 @@ template <> struct Mth<double> {
     }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
     static __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+    static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     static __device__ __forceinline__ double nan_() { return __builtin_nan(""); }

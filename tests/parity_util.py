@@ -48,3 +48,19 @@ def parity_array(dims):
     z = (s // (dims[0] * dims[1])) % dims[2]
     t = s // (dims[0] * dims[1] * dims[2])
     return (x + y + z + t) & 1
+
+
+def update_condition(orc, dims, before, U_new, s, mu):
+    """First-order sensitivity of a heat-bath update to rounding: the link is
+    U' = X W^dag with W = V/k, so a staple error dV moves U' by ~dV/k (V is a
+    sum of six unit-size products, hence 6/k), and X has vector part
+    |a| = sqrt(delta (2 - delta)), so an error in delta moves it by
+    ~d(delta)/|a| as a0 -> -1.  Returns 6/k + 1/|a|, from the oracle's
+    configuration `before` the substep and its new link."""
+    V = orc.staple(dims, before, s, mu)
+    k = float(np.linalg.norm(V))
+    if k == 0.0:
+        return float("inf")
+    a0 = float(orc.qmul(U_new[s, mu], V)[0]) / k
+    a = float(np.sqrt(max(0.0, 1.0 - a0 * a0)))
+    return 6.0 / k + (1.0 / a if a > 0 else float("inf"))

@@ -43,3 +43,15 @@ def test_downstream_matches_brute_force(orc):
                     taint[s, mu] = True
     assert np.array_equal(fast, taint)
     assert taint.sum() > flips.sum()
+
+
+def test_update_condition_closed_form(orc):
+    """Cold 2^4 lattice: every staple is 6 (six identity products), so
+    6/k = 1; for a new link with a0 = cos(0.3) the vector part is sin(0.3)."""
+    dims = (2, 2, 2, 2)
+    U0 = orc.cold(dims)
+    new = U0.copy()
+    new[5, 2] = [np.cos(0.3), 0.0, np.sin(0.3), 0.0]
+    c = parity_util.update_condition(orc, dims, U0, new, 5, 2)
+    assert abs(c - (1.0 + 1.0 / np.sin(0.3))) < 1e-12
+    assert parity_util.update_condition(orc, dims, U0, U0, 5, 2) == float("inf")
