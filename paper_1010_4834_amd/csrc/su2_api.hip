@@ -123,6 +123,9 @@ bool dims_ok(const int *d) {
     for (int k = 0; k < 4; ++k)
         if (d[k] < 2 || (d[k] & 1)) return false;
     long long V = (long long)d[0] * d[1] * d[2] * d[3];
+    // site decompositions multiply quotients back with 24-bit products; the
+    // largest quotient is Ny Nz Nt
+    if ((long long)d[1] * d[2] * d[3] >= (1LL << 24)) return false;
     return V <= MAX_SITES;
 }
 

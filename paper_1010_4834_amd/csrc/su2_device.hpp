@@ -67,6 +67,8 @@ __device__ __forceinline__ uint32_t tag(int lat_id, uint32_t purpose, int mu, in
 // q = n / d, r = n % d for 0 <= n < 2^31, 0 < d < 2^24, with a binary64
 // reciprocal and a one-step correction (the product is within one of the
 // true quotient); q*d < 2^31 so the 24-bit multiply is exact.
+// Requires n / d < 2^24 (the 24-bit product; guaranteed by the extent
+// checks at creation: every quotient is at most Ny Nz Nt < 2^24).
 __device__ __forceinline__ void udiv(int n, int d, double inv, int &q, int &r) {
     int qq = (int)((double)n * inv);
     int rr = n - (int)__umul24((unsigned)qq, (unsigned)d);

@@ -29,7 +29,7 @@ __device__ __forceinline__ Site site_of(const LatDesc &d, int cb, int par) {
     udiv(r2, d.n[2], d.inv_nz, t, z);
     const int x = 2 * j + ((par + y + z + t) & 1);
     S.c[0] = x; S.c[1] = y; S.c[2] = z; S.c[3] = t;
-    S.s = x + d.n[0] * row;
+    S.s = x + (int)__umul24((unsigned)d.n[0], (unsigned)row);  // row < Ny Nz Nt < 2^24
     return S;
 }
 
@@ -37,13 +37,18 @@ __device__ __forceinline__ Site site_of(const LatDesc &d, int cb, int par) {
 __device__ __forceinline__ int stride_of(const LatDesc &d, int mu) {
     return mu == 0 ? 1 : mu == 1 ? d.n[0] : mu == 2 ? d.n[0] * d.n[1] : d.ns;
 }
+// Both candidate steps are uniform; they are pinned as scalars so that the
+// select picks one of them rather than a multiplier of the stride (which
+// would put a 32-bit vector multiply on every neighbour).
 __device__ __forceinline__ int step_fwd(const LatDesc &d, const Site &S, int mu) {
     const int st = stride_of(d, mu);
-    return S.c[mu] == d.n[mu] - 1 ? -(d.n[mu] - 1) * st : st;
+    const int in = uni(st), wrap = uni(-(d.n[mu] - 1) * st);
+    return S.c[mu] == d.n[mu] - 1 ? wrap : in;
 }
 __device__ __forceinline__ int step_bwd(const LatDesc &d, const Site &S, int mu) {
     const int st = stride_of(d, mu);
-    return S.c[mu] == 0 ? (d.n[mu] - 1) * st : -st;
+    const int in = uni(-st), wrap = uni((d.n[mu] - 1) * st);
+    return S.c[mu] == 0 ? wrap : in;
 }
 
 // Uniform bases of the (direction, parity) blocks of one lattice in a link
@@ -244,8 +249,15 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             delta[m] = T(0);
             rec[m] = 0;
         }
-        uint32_t j = 0;
-        while (pend) {
+        // The loop runs while any lane of the wavefront has a link pending;
+        // each pass is one try of every active lane, so the wavefront's try
+        // count is the sum of the active-lane counts (scalar work).
+        uint32_t j = 0, wtries = 0;
+        while (true) {
+            const unsigned long long act = __ballot(pend != 0u);
+            if (act == 0ull) break;
+            wtries += (uint32_t)__popcll(act);
+            if (!pend) continue;
             const int m = __builtin_ctz(pend);
             const int s = pick(sidx, m);
             const T al = pick(alpha, m), ia = pick(ial, m);
@@ -284,7 +296,6 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
 
         // Direction from its own Philox call (try word 0xFFFFFFFF), then
         // U' = X W^dag, renormalised.
-        uint32_t tries = 0;
         double pq = 0.0;
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
@@ -301,7 +312,6 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
                 const Q<T> Un = qnormalize(qmul(X, Wd[m]));
                 sts_(B, MU, par, (uint32_t)cb, Un);
                 if (TRACE) a.trace[d.toff + (long long)sidx[m] * 4 + MU] = rec[m];
-                tries += rec[m] & 0x7FFFFFFFu;
                 if (PLAQ)  // 1/2 Re Tr(U' V_low)
                     pq += (double)(Un.a * Vl[m].a - Un.b * Vl[m].b - Un.c * Vl[m].c - Un.d * Vl[m].d);
             }
@@ -311,8 +321,7 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             if ((threadIdx.x & 63) == 0)
                 plaq_part[(3 * (long long)tile + (MU - 1)) * 4 + (threadIdx.x >> 6)] = pq;
         }
-        tries = wave_sum_u32(tries);
-        if ((threadIdx.x & 63) == 0 && tries) atomicAdd(&a.tries_part[tile], (unsigned long long)tries);
+        if ((threadIdx.x & 63) == 0 && wtries) atomicAdd(&a.tries_part[tile], (unsigned long long)wtries);
         if (!w.next()) break;
         tile = w.tile();
         tl = load_tile(a.tiles, tile);
