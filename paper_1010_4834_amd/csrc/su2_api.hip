@@ -1043,7 +1043,7 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     Timed t(E, SU2_K_WILSON, s);
     su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, Tmax, E->wl_t, E->wl_s,
                        E->block, s);
-    su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_t, E->wl_s, E->wpart, s);
+    su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_t, E->wl_s, E->wpart, E->block, s);
     double *dout = nullptr;
     CHK(dalloc(E, &dout, sizeof(double) * Rmax * Tmax));
     su2::launch_wfinal(E->ddesc, E->nvtiles, Rmax, Tmax, E->wpart, dout, s);

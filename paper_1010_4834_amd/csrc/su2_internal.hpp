@@ -62,7 +62,7 @@ void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *ds
 void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,
                    void *sl, int block, hipStream_t s);
 void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
-                   hipStream_t s);
+                   int block, hipStream_t s);
 void launch_wfinal(const LatDesc *desc, int ntiles, int Rmax, int Tmax, const double *part, double *out,
                    hipStream_t s);
 

@@ -703,8 +703,38 @@ __global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const doubl
 // U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag and the backward staple
 // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)] with a binary64 norm.
 // src_raw: read the lattice links (first step) or the smeared buffer.
+// Grid row blockIdx.y = 3 * parity + mu: one link per lane, so the six
+// (parity, direction) classes run as independent wavefronts.
+template <class T, int MU>
+__device__ __forceinline__ void ape_link(const LatDesc &d, const Blocks<T, 3> &Bs, const Blocks<T, 3> &Bd,
+                                         int cb, int par, T alpha) {
+    const Site S = site_of(d, cb, par);
+    const int op = par ^ 1;
+    const int s_mu = S.s + step_fwd(d, S, MU);
+    Q<T> sum{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int nu = 0; nu < 3; ++nu) {
+        if (nu == MU) continue;
+        const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
+        const Q<T> a1 = lds_(Bs, nu, par, (uint32_t)S.s >> 1);
+        const Q<T> a2 = lds_(Bs, MU, op, (uint32_t)(S.s + fn) >> 1);
+        const Q<T> a3 = lds_(Bs, nu, op, (uint32_t)s_mu >> 1);
+        const Q<T> b1 = lds_(Bs, nu, op, (uint32_t)(S.s + bn) >> 1);
+        const Q<T> b2 = lds_(Bs, MU, op, (uint32_t)(S.s + bn) >> 1);
+        const Q<T> b3 = lds_(Bs, nu, par, (uint32_t)(s_mu + bn) >> 1);
+        qacc(sum, qmul(qmul(a1, a2), qdag(a3)));
+        qacc(sum, qmul(qmul(qdag(b1), b2), b3));
+    }
+    const Q<T> u = lds_(Bs, MU, par, (uint32_t)cb);
+    const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
+    const Q<T> w{w0 * u.a + w1 * sum.a, w0 * u.b + w1 * sum.b, w0 * u.c + w1 * sum.c, w0 * u.d + w1 * sum.d};
+    const double n2 = (double)w.a * w.a + (double)w.b * w.b + (double)w.c * w.c + (double)w.d * w.d;
+    sts_(Bd, MU, par, (uint32_t)cb, n2 > 0.0 ? qnormalize(w) : u);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_raw, void *dst, T alpha) {
+    const int par = (int)blockIdx.y / 3, mu = (int)blockIdx.y % 3;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tl = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tl.x);
@@ -712,35 +742,9 @@ __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_r
         const Blocks<T, 3> Bd = blocks<T, 3>(dst, d.soff, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        for (int par = 0; par < 2; ++par) {
-            const Site S = site_of(d, cb, par);
-            const int op = par ^ 1;
-#pragma unroll
-            for (int mu = 0; mu < 3; ++mu) {
-                const int s_mu = S.s + step_fwd(d, S, mu);
-                Q<T> sum{T(0), T(0), T(0), T(0)};
-#pragma unroll
-                for (int nu = 0; nu < 3; ++nu) {
-                    if (nu == mu) continue;
-                    const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
-                    const Q<T> a1 = lds_(Bs, nu, par, (uint32_t)S.s >> 1);
-                    const Q<T> a2 = lds_(Bs, mu, op, (uint32_t)(S.s + fn) >> 1);
-                    const Q<T> a3 = lds_(Bs, nu, op, (uint32_t)s_mu >> 1);
-                    qacc(sum, qmul(qmul(a1, a2), qdag(a3)));
-                    const Q<T> b1 = lds_(Bs, nu, op, (uint32_t)(S.s + bn) >> 1);
-                    const Q<T> b2 = lds_(Bs, mu, op, (uint32_t)(S.s + bn) >> 1);
-                    const Q<T> b3 = lds_(Bs, nu, par, (uint32_t)(s_mu + bn) >> 1);
-                    qacc(sum, qmul(qmul(qdag(b1), b2), b3));
-                }
-                const Q<T> u = lds_(Bs, mu, par, (uint32_t)cb);
-                const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
-                const Q<T> w{w0 * u.a + w1 * sum.a, w0 * u.b + w1 * sum.b, w0 * u.c + w1 * sum.c,
-                             w0 * u.d + w1 * sum.d};
-                const double n2 = (double)w.a * w.a + (double)w.b * w.b + (double)w.c * w.c +
-                                  (double)w.d * w.d;
-                sts_(Bd, mu, par, (uint32_t)cb, n2 > 0.0 ? qnormalize(w) : u);
-            }
-        }
+        if (mu == 0) ape_link<T, 0>(d, Bs, Bd, cb, par, alpha);
+        else if (mu == 1) ape_link<T, 1>(d, Bs, Bd, cb, par, alpha);
+        else ape_link<T, 2>(d, Bs, Bd, cb, par, alpha);
     });
 }
 
@@ -989,10 +993,9 @@ void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s) {
-    if (f32)
-        hipLaunchKernelGGL((k_ape<float>), grid_of(a, grid), dim3(block), 0, s, a, src, src_raw, dst, (float)alpha);
-    else
-        hipLaunchKernelGGL((k_ape<double>), grid_of(a, grid), dim3(block), 0, s, a, src, src_raw, dst, alpha);
+    const dim3 g(grid_of(a, grid).x, 6);  // y: 3 * parity + spatial mu
+    if (f32) hipLaunchKernelGGL((k_ape<float>), g, dim3(block), 0, s, a, src, src_raw, dst, (float)alpha);
+    else hipLaunchKernelGGL((k_ape<double>), g, dim3(block), 0, s, a, src, src_raw, dst, alpha);
 }
 
 void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,
@@ -1005,22 +1008,24 @@ void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rma
                            (Q<double> *)tl, (Q<double> *)sl);
 }
 
+// `block` must be the site-tile size of the tile table: a workgroup sums
+// exactly the sites of its tile.
 template <class T>
 static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
-                            hipStream_t s) {
-    dim3 g(grid_of(a, 0).x, (unsigned)Rmax);
+                            int block, hipStream_t s) {
+    dim3 g(grid_of(a, 0).x, (unsigned)Rmax), b((unsigned)block);
     const Q<T> *t = (const Q<T> *)tl;
     const Q<T> *l = (const Q<T> *)sl;
-    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4>), g, dim3(256), 0, s, a, Rmax, Tmax, t, l, part);
-    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8>), g, dim3(256), 0, s, a, Rmax, Tmax, t, l, part);
-    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16>), g, dim3(256), 0, s, a, Rmax, Tmax, t, l, part);
-    else hipLaunchKernelGGL((k_wtrace<T, 32>), g, dim3(256), 0, s, a, Rmax, Tmax, t, l, part);
+    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
+    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
+    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
+    else hipLaunchKernelGGL((k_wtrace<T, 32>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
 }
 
 void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
-                   hipStream_t s) {
-    if (f32) launch_wtrace_t<float>(a, Rmax, Tmax, tl, sl, part, s);
-    else launch_wtrace_t<double>(a, Rmax, Tmax, tl, sl, part, s);
+                   int block, hipStream_t s) {
+    if (f32) launch_wtrace_t<float>(a, Rmax, Tmax, tl, sl, part, block, s);
+    else launch_wtrace_t<double>(a, Rmax, Tmax, tl, sl, part, block, s);
 }
 
 void launch_wfinal(const LatDesc *desc, int ntiles, int Rmax, int Tmax, const double *part, double *out,

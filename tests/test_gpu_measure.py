@@ -60,6 +60,27 @@ def test_ape_and_wilson(su2, orc, dims):
         lat.close()
 
 
+@pytest.mark.parametrize("launch", [(64, 0, 1, 2), (128, 16, 0, 4), (192, 8, 1, 1), (256, 0, 1, 1)])
+def test_measurements_any_launch_shape(su2, orc, launch):
+    """Plaquette, Polyakov loop, APE smearing and Wilson loops agree with the
+    oracle under every launch shape (block size = tile size of the
+    measurement kernels)."""
+    dims = (6, 4, 10, 6)
+    U = inputs.random_config(dims, 43)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
+    su2.su2_set_launch(lat.h, *launch)
+    lat.set_links(U)
+    P = lat.plaquette()
+    assert np.abs(np.array(P) - np.array(orc.plaquette(dims, U))).max() < 1e-13
+    assert abs(lat.polyakov() - orc.polyakov(dims, U)) < 1e-13
+    lat.ape_smear(0.5, 3)
+    So = orc.ape(dims, U, 0.5, 3)
+    assert np.abs(lat.get_smeared() - So).max() < 1e-12
+    W = lat.wilson_loops(4, 5)
+    assert np.abs(W - orc.wilson(dims, U, 4, 5, So)).max() < 1e-13
+    lat.close()
+
+
 def test_c4_full_size_sampled(su2, orc):
     """24^3 x 48, beta = 2.5, hot start seed 4: APE alpha = 0.7 x 25 on the
     spatial links, W(R <= 12, T <= 16); sampled (R, T) against the oracle."""
