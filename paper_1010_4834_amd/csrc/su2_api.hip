@@ -1032,13 +1032,14 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
         CHK(dalloc(E, &E->wl_s, sb));
         E->wl_s_bytes = sb;
     }
-    const size_t pb = sizeof(double) * 2 * (size_t)Rmax * E->nvtiles * Tmax;
+    const KArgs va = kargs(E, 2);
+    const int nparts = su2::wtrace_groups(va);
+    const size_t pb = sizeof(double) * 2 * (size_t)Rmax * nparts * Tmax;
     if (pb > E->wpart_bytes) {
         CHK(dalloc(E, &E->wpart, pb));
         E->wpart_bytes = pb;
     }
     hipStream_t s = E->stream();
-    const KArgs va = kargs(E, 2);
     const bool sm = E->sm_cur >= 0;
     Timed t(E, SU2_K_WILSON, s);
     su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, Tmax, E->wl_t, E->wl_s,
@@ -1046,7 +1047,7 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_t, E->wl_s, E->wpart, E->block, s);
     double *dout = nullptr;
     CHK(dalloc(E, &dout, sizeof(double) * Rmax * Tmax));
-    su2::launch_wfinal(E->ddesc, E->nvtiles, Rmax, Tmax, E->wpart, dout, s);
+    su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout, s);
     t.done(s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, dout, sizeof(double) * Rmax * Tmax, hipMemcpyDeviceToHost, s));

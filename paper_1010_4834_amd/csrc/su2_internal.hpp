@@ -63,7 +63,9 @@ void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rma
                    void *sl, int block, hipStream_t s);
 void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
                    int block, hipStream_t s);
-void launch_wfinal(const LatDesc *desc, int ntiles, int Rmax, int Tmax, const double *part, double *out,
+// Workgroups per R of the Wilson-loop trace launch (its partials per R).
+int wtrace_groups(const KArgs &a);
+void launch_wfinal(const LatDesc *desc, int nparts, int Rmax, int Tmax, const double *part, double *out,
                    hipStream_t s);
 
 }  // namespace su2

@@ -703,8 +703,8 @@ __global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const doubl
 // U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag and the backward staple
 // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)] with a binary64 norm.
 // src_raw: read the lattice links (first step) or the smeared buffer.
-// Grid row blockIdx.y = 3 * parity + mu: one link per lane, so the six
-// (parity, direction) classes run as independent wavefronts.
+// Grid row blockIdx.y = parity; a lane updates the three spatial links of
+// its site, which share several of their staple loads.
 template <class T, int MU>
 __device__ __forceinline__ void ape_link(const LatDesc &d, const Blocks<T, 3> &Bs, const Blocks<T, 3> &Bd,
                                          int cb, int par, T alpha) {
@@ -734,7 +734,7 @@ __device__ __forceinline__ void ape_link(const LatDesc &d, const Blocks<T, 3> &B
 
 template <class T>
 __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_raw, void *dst, T alpha) {
-    const int par = (int)blockIdx.y / 3, mu = (int)blockIdx.y % 3;
+    const int par = (int)blockIdx.y;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tl = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tl.x);
@@ -742,9 +742,9 @@ __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_r
         const Blocks<T, 3> Bd = blocks<T, 3>(dst, d.soff, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        if (mu == 0) ape_link<T, 0>(d, Bs, Bd, cb, par, alpha);
-        else if (mu == 1) ape_link<T, 1>(d, Bs, Bd, cb, par, alpha);
-        else ape_link<T, 2>(d, Bs, Bd, cb, par, alpha);
+        ape_link<T, 0>(d, Bs, Bd, cb, par, alpha);
+        ape_link<T, 1>(d, Bs, Bd, cb, par, alpha);
+        ape_link<T, 2>(d, Bs, Bd, cb, par, alpha);
     });
 }
 
@@ -798,21 +798,22 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
 
 // W(R,T) partials: blockIdx.y = R-1; per site and spatial mu,
 // 1/2 Tr[S(x;R) T(x+R mu;T) S(x+T t;R)^dag T(x;T)^dag]
-// = 1/2 Tr[(S(x;R) T(x+R mu;T)) (T(x;T) S(x+T t;R))^dag], summed over mu in
-// binary64 per lane, then a compensated block sum per (R, tile, T).
+// = 1/2 Tr[(S(x;R) T(x+R mu;T)) (T(x;T) S(x+T t;R))^dag].  A workgroup walks
+// its share of the site tiles (a fixed assignment), each lane summing its
+// sites in binary64, then one compensated block sum per (R, workgroup, T).
 template <class T, int TMAX>
 __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, const Q<T> *tl, const Q<T> *sl,
                                                 double *part) {
     __shared__ DD lds[TMAX * 4];
     const int R = blockIdx.y + 1;
+    double sum[TMAX];
+#pragma unroll
+    for (int k = 0; k < TMAX; ++k) sum[k] = 0.0;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tv = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tv.x);
         const int s = tv.y + (int)threadIdx.x;
         const long long V = 2LL * d.vh;
-        DD acc[TMAX];
-#pragma unroll
-        for (int k = 0; k < TMAX; ++k) acc[k] = DD{0.0, 0.0};
         if (s < V) {
             int c[4], r = s;
             udiv(r, d.n[0], d.inv_nx, r, c[0]);
@@ -842,23 +843,27 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, con
                         const Q<T> s2 = sl[((long long)mu * Rmax + R - 1) * V + sT];
                         v += (double)half_tr_xyd(qmul(S0[mu], t1), qmul(t0, s2));
                     }
-                    acc[k] = DD{v, 0.0};
+                    sum[k] += v;
                 }
             }
         }
-        dd_block_sum<TMAX>(acc, lds);
-        if (threadIdx.x == 0)
-#pragma unroll
-            for (int k = 0; k < TMAX; ++k)
-                if (k < Tmax) {
-                    double *p = part + 2 * (((long long)(R - 1) * a.ntiles + tile) * Tmax + k);
-                    p[0] = acc[k].hi;
-                    p[1] = acc[k].lo;
-                }
     });
+    DD acc[TMAX];
+#pragma unroll
+    for (int k = 0; k < TMAX; ++k) acc[k] = DD{sum[k], 0.0};
+    dd_block_sum<TMAX>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < TMAX; ++k)
+            if (k < Tmax) {
+                double *p = part + 2 * (((long long)(R - 1) * gridDim.x + blockIdx.x) * Tmax + k);
+                p[0] = acc[k].hi;
+                p[1] = acc[k].lo;
+            }
 }
 
-// One block per (R, T): fixed-order sum over the tiles of lattice 0.
+// One block per (R, T): fixed-order sum over the k_wtrace workgroups'
+// partials (nparts per R) of lattice 0.
 __global__ __launch_bounds__(256) void k_wfinal(const LatDesc *desc, int ntiles, int Tmax, const double *part,
                                                 double *out) {
     __shared__ DD lds[4];
@@ -993,7 +998,7 @@ void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s) {
-    const dim3 g(grid_of(a, grid).x, 6);  // y: 3 * parity + spatial mu
+    const dim3 g(grid_of(a, grid).x, 2);  // y: parity
     if (f32) hipLaunchKernelGGL((k_ape<float>), g, dim3(block), 0, s, a, src, src_raw, dst, (float)alpha);
     else hipLaunchKernelGGL((k_ape<double>), g, dim3(block), 0, s, a, src, src_raw, dst, alpha);
 }
@@ -1009,11 +1014,17 @@ void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rma
 }
 
 // `block` must be the site-tile size of the tile table: a workgroup sums
-// exactly the sites of its tile.
+// exactly the sites of its tiles.  Workgroups per R: enough to fill the
+// chip a few times over, each taking several tiles (a multiple of 8).
+int wtrace_groups(const KArgs &a) {
+    const int g = ((a.ntiles + 7) / 8) * 8;
+    return g < 1024 ? (g < 8 ? 8 : g) : 1024;
+}
+
 template <class T>
 static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
                             int block, hipStream_t s) {
-    dim3 g(grid_of(a, 0).x, (unsigned)Rmax), b((unsigned)block);
+    dim3 g(wtrace_groups(a), (unsigned)Rmax), b((unsigned)block);
     const Q<T> *t = (const Q<T> *)tl;
     const Q<T> *l = (const Q<T> *)sl;
     if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
@@ -1028,9 +1039,9 @@ void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl,
     else launch_wtrace_t<double>(a, Rmax, Tmax, tl, sl, part, block, s);
 }
 
-void launch_wfinal(const LatDesc *desc, int ntiles, int Rmax, int Tmax, const double *part, double *out,
+void launch_wfinal(const LatDesc *desc, int nparts, int Rmax, int Tmax, const double *part, double *out,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_wfinal, dim3((unsigned)(Rmax * Tmax)), dim3(256), 0, s, desc, ntiles, Tmax, part, out);
+    hipLaunchKernelGGL(k_wfinal, dim3((unsigned)(Rmax * Tmax)), dim3(256), 0, s, desc, nparts, Tmax, part, out);
 }
 
 }  // namespace su2
