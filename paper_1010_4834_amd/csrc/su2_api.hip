@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -651,16 +652,29 @@ su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, 
 // Time one sweep per candidate shape; links, sweep counter and tries are
 // restored afterwards.
 struct Shape { int block, grid, remap, nl; };
+// Shapes found per size class; shared by all handles of the process.
 std::map<std::string, Shape> g_tune_cache;
+std::mutex g_tune_mutex;
+
+bool tune_cache_get(const std::string &key, Shape &out) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void tune_cache_put(const std::string &key, const Shape &v) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = v;
+}
 
 su2_status autotune_common(su2_ensemble_s *E) {
     char key[160];
     std::snprintf(key, sizeof key, "%s:n%d:sites%lld:t%lld", E->f32 ? "f32" : "f64", E->n, E->total_sites,
                   (long long)E->hdesc[0].n[3]);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-        return set_launch_common(E, it->second.block, it->second.grid, it->second.remap, it->second.nl);
-    }
+    Shape cached;
+    if (tune_cache_get(key, cached)) return set_launch_common(E, cached.block, cached.grid, cached.remap, cached.nl);
 
     hipStream_t s = E->stream();
     void *backup = nullptr;
@@ -718,7 +732,7 @@ su2_status autotune_common(su2_ensemble_s *E) {
     E->hst = st0;
     CHK(upload_state(E));
     E->timing = timing0;
-    g_tune_cache[key] = bestc;
+    tune_cache_put(key, bestc);
     invalidate_measure_buffers(E);
     return SU2_OK;
 }

@@ -271,14 +271,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t t) {
-    t += swz_xor<1>(t);
-    t += swz_xor<2>(t);
-    t += swz_xor<4>(t);
-    t += swz_xor<8>(t);
-    t += swz_xor<16>(t);
-    return (uint32_t)__builtin_amdgcn_readlane((int)t, 0) + (uint32_t)__builtin_amdgcn_readlane((int)t, 32);
-}
 __device__ __forceinline__ double wave_sum_f64(double v) {
     v += swz_xor<1>(v);
     v += swz_xor<2>(v);
