@@ -34,7 +34,8 @@
  *    call with try word 0xFFFFFFFF for the direction of its vector part.
  *    One heat-bath sweep consumes the counters of one sweep index;
  *    each lattice keeps a sweep counter so successive calls continue the
- *    stream.  Results do not depend on launch shapes.
+ *    stream.  Link updates do not depend on launch shapes (bit for bit);
+ *    reductions agree up to the rounding of their summation order.
  */
 #ifndef SU2_H
 #define SU2_H
@@ -73,7 +74,7 @@ typedef enum {
     SU2_K_OVERRELAX = 1,
     SU2_K_PLAQUETTE = 2,
     SU2_K_POLYAKOV = 3,
-    SU2_K_REDUCE = 4,   /* final per-lattice reductions           */
+    SU2_K_REDUCE = 4,   /* final reductions (measurements, series) */
     SU2_K_APE = 5,
     SU2_K_WILSON = 6,
     SU2_K_COUNT = 7
@@ -186,7 +187,8 @@ su2_status su2_load(const char *path, su2_lattice *out);
  * workgroups of the persistent grid (0 = one workgroup per tile; else a
  * multiple of 8), whether tiles are laid out per XCD (1) or round-robin (0),
  * and heat-bath links per lane (1, 2 or 4: a lane draws its links in one
- * rejection loop).  Results do not depend on it.  EINVAL for other values. */
+ * rejection loop).  Link updates do not depend on it; reductions only in
+ * rounding.  EINVAL for other values. */
 su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap, int links_per_lane);
 su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap, int *links_per_lane);
 /* Time the candidate launch shapes on this lattice and keep the fastest
@@ -217,8 +219,11 @@ su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
 /* nsweeps heat-bath sweeps of every lattice at its own beta, with the mean
  * plaquette and Polyakov loop of every lattice after every sweep written to
  * plaq[i*nsweeps + k] and poly[i*nsweeps + k] (either may be NULL to skip
- * that measurement).  One sweep plus its measurements is captured once in a
- * HIP graph and replayed; the series stay on the device until the end. */
+ * that measurement).  One sweep (eight substep launches; the plaquette is
+ * summed inside the odd substeps) is captured once in a HIP graph and
+ * replayed; per-sweep partial sums are reduced once per batch of up to 512
+ * sweeps, and the series stay on the device until the end.  Measuring does
+ * not change the Markov chain. */
 su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, uint64_t seed, double *plaq,
                             double *poly);
 su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
