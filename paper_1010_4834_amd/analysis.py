@@ -83,3 +83,19 @@ def static_potential(Wcfg, t0, rmin, rmax, nbins):
     return {"R": R, "V": V, "dV": dV, "A": coef[0], "B": coef[1], "sigma": coef[2],
             "dA": dcoef[0], "dB": dcoef[1], "dsigma": dcoef[2], "t0": t0, "rmin": rmin, "rmax": rmax,
             "nbins": nbins}
+
+
+def stable_t0(Wcfg, rmin, rmax, nbins, tmin=2):
+    """Plateau choice for static_potential: the smallest t0 >= tmin whose
+    fitted sigma a^2 agrees with the t0 + 1 fit within the t0 + 1 fit's
+    jackknife error (excited states have decayed to within the noise).
+    None if no t0 qualifies."""
+    Wcfg = np.asarray(Wcfg, dtype=np.float64)
+    prev = None
+    for t0 in range(tmin, Wcfg.shape[2]):
+        res = static_potential(Wcfg, t0, rmin, rmax, nbins)
+        if prev is not None and abs(res["sigma"] - prev["sigma"]) <= res["dsigma"]:
+            return prev["t0"]
+        prev = res
+    return None
+

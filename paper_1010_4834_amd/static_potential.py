@@ -71,17 +71,24 @@ def main(argv=None):
     ap.add_argument("--ape-alpha", type=float, default=APE_ALPHA)
     ap.add_argument("--rmax", type=int, default=10)
     ap.add_argument("--tmax", type=int, default=12)
-    ap.add_argument("--t0", type=int, default=4)
+    ap.add_argument("--t0", default="4", help="T of the ratio W(R,T)/W(R,T+1), or 'auto' (analysis.stable_t0)")
     ap.add_argument("--rmin-fit", type=int, default=2)
     ap.add_argument("--rmax-fit", type=int, default=10)
     ap.add_argument("--nbins", type=int, default=20)
     ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--save-bins", default=None,
+                    help="write the binned W(R,T) series (nbins x Rmax x Tmax) to this .npy file")
     args = ap.parse_args(argv)
     from . import su2
     dims = tuple(int(x) for x in args.dims.split(","))
     W = measure(dims, args.beta, args.seed, args.ntherm, args.nconf, args.nsep, args.overrelax,
                 args.ape_alpha, args.ape_steps, args.rmax, args.tmax, su2.F64 if args.fp64 else su2.F32)
-    res = analysis.static_potential(W, args.t0, args.rmin_fit, args.rmax_fit, args.nbins)
+    if args.save_bins:
+        np.save(args.save_bins, analysis.bin_series(W, args.nbins))
+    t0 = (analysis.stable_t0(W, args.rmin_fit, args.rmax_fit, args.nbins) if args.t0 == "auto" else int(args.t0))
+    if t0 is None:
+        raise SystemExit("no stable t0: more configurations or a larger Tmax needed")
+    res = analysis.static_potential(W, t0, args.rmin_fit, args.rmax_fit, args.nbins)
     res["a_fm"] = lattice_spacing_fm(res["sigma"]) if res["sigma"] > 0 else float("nan")
     print(json.dumps({k: (v.tolist() if isinstance(v, np.ndarray) else float(v) if isinstance(v, np.floating)
                           else v) for k, v in res.items()}))

@@ -75,3 +75,26 @@ def test_static_potential_rejects_bad_ranges():
         an.static_potential(W, t0=4, rmin=1, rmax=4, nbins=5)
     with pytest.raises(ValueError):
         an.static_potential(W, t0=1, rmin=3, rmax=3, nbins=5)
+
+
+def test_stable_t0_waits_for_the_excited_state():
+    """W = c0 e^{-V T} + c1 e^{-(V + gap) T} with an excited-state weight c1
+    growing with R (as ground-state overlaps fall with R): the effective
+    potential approaches V from above, most at large R, which biases sigma
+    upwards at small t0; the chosen t0 is where the excited state has decayed
+    below the noise, and the fit there recovers sigma."""
+    rng = np.random.default_rng(6)
+    nconf, Rmax, Tmax = 400, 8, 14
+    R = np.arange(1, Rmax + 1, dtype=float)[:, None]
+    T = np.arange(1, Tmax + 1, dtype=float)[None, :]
+    V = cornell(R)
+    c1 = 0.05 * R
+    W0 = (1 - c1) * np.exp(-V * T) + c1 * np.exp(-(V + 0.5) * T)
+    noise = 1.0 + 0.003 * rng.normal(size=(nconf, Rmax, 1)) + 0.002 * rng.normal(size=(nconf, Rmax, Tmax))
+    Wc = W0[None] * noise
+    t0 = an.stable_t0(Wc, 2, 8, 40)
+    assert t0 is not None and t0 >= 4
+    res = an.static_potential(Wc, t0, 2, 8, 40)
+    assert abs(res["sigma"] - 0.0366) < 4 * res["dsigma"] + 5e-4
+    # at t0 = 1 the excited state biases sigma upwards
+    assert an.static_potential(Wc, 1, 2, 8, 40)["sigma"] > res["sigma"] + 3 * res["dsigma"]
