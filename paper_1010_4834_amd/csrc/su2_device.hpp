@@ -117,13 +117,22 @@ template <class T> __device__ __forceinline__ Q<T> qone() { return Q<T>{T(1), T(
 // in binary64 (the reunitarisation that keeps binary32 links on the group).
 // Updated links have |1 - n2| ~ 1e-7, where 1 - e/2 + 3e^2/8 (e = n2 - 1)
 // equals 1/sqrt(n2) to O(e^3); farther from the group the exact form is used.
+// The exact form sits behind a wavefront-uniform branch: as a plain per-lane
+// branch it is if-converted, and every lane then pays for a binary64 square
+// root and division whose result it discards.  The empty volatile asm (no
+// instruction) keeps the compiler from speculating the rare block back onto
+// the common path.
 template <class T> __device__ __forceinline__ Q<T> qnormalize(const Q<T> &x) {
     const double a = x.a, b = x.b, c = x.c, d = x.d;
     const double n2 = a * a + b * b + c * c + d * d;
     const double e = n2 - 1.0;
-    double f;
-    if (fabs(e) < 1e-4) f = 1.0 - e * (0.5 - 0.375 * e);
-    else f = 1.0 / sqrt(n2);
+    const bool near = fabs(e) < 1e-4;
+    double f = 1.0 - e * (0.5 - 0.375 * e);
+    if (__ballot(!near)) {
+        double g = 1.0 / sqrt(n2);
+        __asm__ volatile("" : "+v"(g));
+        if (!near) f = g;
+    }
     return Q<T>{(T)(a * f), (T)(b * f), (T)(c * f), (T)(d * f)};
 }
 

@@ -241,6 +241,22 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             }
         }
 
+        // Creutz factor -expm1(-2 alpha) per link, formed only when a lane of
+        // the wavefront samples with Creutz (as a loop invariant it would
+        // otherwise be hoisted and evaluated for every link).
+        T cfv[NL];
+        bool creutz_any = false;
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            cfv[m] = T(0);
+            creutz_any |= ((pend >> m) & 1u) && ((a.sampler == 1) || !(alpha[m] >= T(2)));
+        }
+        if (__ballot(creutz_any)) {
+#pragma unroll
+            for (int m = 0; m < NL; ++m)
+                if (((pend >> m) & 1u) && alpha[m] >= T(1e-20)) cfv[m] = -M::expm1_(T(-2) * alpha[m]);
+        }
+
         // Rejection loop: a lane moves to its next link when one is accepted.
         T delta[NL];
         uint32_t rec[NL];
@@ -268,7 +284,7 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             if (creutz) {
                 const T u1 = M::u(wd.x), u2 = M::u(wd.y);
                 if (al >= T(1e-20)) {
-                    const T cf = -M::expm1_(T(-2) * al);
+                    const T cf = pick(cfv, m);
                     dl = -M::log1p_(-(T(1) - u1) * cf) * ia;
                 } else {
                     dl = T(2) * (T(1) - u1);
