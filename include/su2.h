@@ -94,7 +94,7 @@ size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec);
  * Sec. 2).  The hot start draws Philox purpose 1 with `seed`.
  * device_links: optional caller-owned device buffer of su2_link_bytes()
  * bytes (NULL: the library allocates).  EINVAL on odd or < 2 extents, a
- * volume above 2^30 sites, Ny*Nz*Nt >= 2^24, or a bad enum; ENODEV
+ * volume above 2^30 sites, Ny*Nz*Nt >= 2^24 or Nx >= 2^24, or a bad enum; ENODEV
  * without a GPU. */
 su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t seed,
                       su2_prec prec, void *device_links, size_t device_bytes,

@@ -124,11 +124,15 @@ bool dims_ok(const int *d) {
     for (int k = 0; k < 4; ++k)
         if (d[k] < 2 || (d[k] & 1)) return false;
     long long V = (long long)d[0] * d[1] * d[2] * d[3];
-    // site decompositions multiply quotients back with 24-bit products; the
-    // largest quotient is Ny Nz Nt
-    if ((long long)d[1] * d[2] * d[3] >= (1LL << 24)) return false;
+    // site decompositions multiply quotients and divisors back with 24-bit
+    // products; the largest quotient is Ny Nz Nt, the largest divisor Nx
+    if ((long long)d[1] * d[2] * d[3] >= (1LL << 24) || d[0] >= (1 << 24)) return false;
     return V <= MAX_SITES;
 }
+
+// 1/d rounded up to the next binary64, the reciprocal the device division
+// helper needs to truncate to floor(n/d) without a correction step.
+double recip_up(int d) { return std::nextafter(1.0 / d, HUGE_VAL); }
 
 su2_status enter(su2_ensemble_s *E) {
     if (!E) return SU2_EINVAL;
@@ -360,10 +364,10 @@ su2_status create_common(int n, const int *dims, const double *betas, su2_start 
         D.off = off;
         D.soff = 3 * sites;
         D.toff = off;
-        D.inv_hx = 1.0 / D.hx;
-        D.inv_nx = 1.0 / d[0];
-        D.inv_ny = 1.0 / d[1];
-        D.inv_nz = 1.0 / d[2];
+        D.inv_hx = recip_up(D.hx);
+        D.inv_nx = recip_up(d[0]);
+        D.inv_ny = recip_up(d[1]);
+        D.inv_nz = recip_up(d[2]);
         D.beta = betas ? betas[l] : 0.0;
         D.betaf = (float)D.beta;
         off += 4 * V;

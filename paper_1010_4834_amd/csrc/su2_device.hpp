@@ -64,18 +64,18 @@ __device__ __forceinline__ uint32_t tag(int lat_id, uint32_t purpose, int mu, in
     return ((uint32_t)lat_id << 8) | (purpose << 4) | ((uint32_t)mu << 1) | (uint32_t)parity;
 }
 
-// q = n / d, r = n % d for 0 <= n < 2^31, 0 < d < 2^24, with a binary64
-// reciprocal and a one-step correction (the product is within one of the
-// true quotient); q*d < 2^31 so the 24-bit multiply is exact.
-// Requires n / d < 2^24 (the 24-bit product; guaranteed by the extent
-// checks at creation: every quotient is at most Ny Nz Nt < 2^24).
+// q = n / d, r = n % d for 0 <= n < 2^31, 0 < d < 2^24 and n / d < 2^24,
+// with no correction step.  inv is 1/d rounded up to the next binary64
+// (the host stores it so), at most (1 + 3 2^-53)/d.  The rounded product
+// n inv is then at least n/d (rounding is monotone and n/d <= n inv) and
+// exceeds it by less than 2^-27, below the distance 1/d > 2^-24 from a
+// non-integer n/d to the next integer; truncating it gives floor(n/d).
+// q d <= n < 2^31, so the 24-bit multiply is exact.  The extent checks at
+// creation guarantee the bounds (every quotient is at most Ny Nz Nt < 2^24,
+// every divisor at most Nx < 2^24).
 __device__ __forceinline__ void udiv(int n, int d, double inv, int &q, int &r) {
-    int qq = (int)((double)n * inv);
-    int rr = n - (int)__umul24((unsigned)qq, (unsigned)d);
-    if (rr < 0) { --qq; rr += d; }
-    else if (rr >= d) { ++qq; rr -= d; }
-    q = qq;
-    r = rr;
+    q = (int)((double)n * inv);
+    r = n - (int)__umul24((unsigned)q, (unsigned)d);
 }
 
 // ---------------------------------------------------------------------------

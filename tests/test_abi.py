@@ -31,7 +31,7 @@ def test_host_validation():
     from paper_1010_4834_amd import su2
     assert su2.su2_link_bytes(8, 8, 8, 8, su2.F32) == 4 * 8**4 * 16
     assert su2.su2_link_bytes(8, 8, 8, 8, su2.F64) == 4 * 8**4 * 32
-    for bad in ((7, 8, 8, 8), (8, 8, 8, 0), (8, 1, 8, 8), (2, 256, 256, 256)):
+    for bad in ((7, 8, 8, 8), (8, 8, 8, 0), (8, 1, 8, 8), (2, 256, 256, 256), (1 << 24, 2, 2, 2)):
         assert su2.su2_link_bytes(*bad, su2.F32) == 0
         with pytest.raises(su2.SU2Error) as e:
             su2.su2_create(*bad, su2.COLD, 1, su2.F32)
