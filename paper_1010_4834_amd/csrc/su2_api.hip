@@ -80,8 +80,8 @@ struct su2_ensemble_s {
     void *sm[2] = {nullptr, nullptr};
     int sm_cur = -1;  // index of the valid smeared buffer, -1 none
 
-    void *wl_t = nullptr, *wl_s = nullptr;
-    size_t wl_t_bytes = 0, wl_s_bytes = 0;
+    void *wl_s = nullptr;  // spatial lines of the Wilson loops
+    size_t wl_s_bytes = 0;
     double *wpart = nullptr;
     size_t wpart_bytes = 0;
 
@@ -416,7 +416,7 @@ void destroy_common(su2_ensemble_s *E) {
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
     void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->st, E->tries_part, E->part_plaq,
-                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1], E->wl_t,
+                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1],
                     E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -1041,11 +1041,7 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     if (!out || Rmax < 1 || Tmax < 1 || Rmax > smin || Tmax > d.n[3] || Tmax > 32) return SU2_EINVAL;
     const size_t qb = link_size(E->f32);
     const long long V = E->total_sites;
-    const size_t tb = qb * (size_t)Tmax * V, sb = qb * (size_t)3 * Rmax * V;
-    if (tb > E->wl_t_bytes) {
-        CHK(dalloc(E, &E->wl_t, tb));
-        E->wl_t_bytes = tb;
-    }
+    const size_t sb = qb * (size_t)3 * Rmax * V;
     if (sb > E->wl_s_bytes) {
         CHK(dalloc(E, &E->wl_s, sb));
         E->wl_s_bytes = sb;
@@ -1060,9 +1056,8 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     hipStream_t s = E->stream();
     const bool sm = E->sm_cur >= 0;
     Timed t(E, SU2_K_WILSON, s);
-    su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, Tmax, E->wl_t, E->wl_s,
-                       E->block, s);
-    su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_t, E->wl_s, E->wpart, E->block, s);
+    su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, E->wl_s, E->block, s);
+    su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_s, E->wpart, E->block, s);
     double *dout = nullptr;
     CHK(dalloc(E, &dout, sizeof(double) * Rmax * Tmax));
     su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout, s);

@@ -59,10 +59,10 @@ void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp
                    long long ostride, int out0, hipStream_t s);
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s);
-void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,
-                   void *sl, int block, hipStream_t s);
-void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
-                   int block, hipStream_t s);
+void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, void *sl, int block,
+                   hipStream_t s);
+void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *sl, double *part, int block,
+                   hipStream_t s);
 // Workgroups per R of the Wilson-loop trace launch (its partials per R).
 int wtrace_groups(const KArgs &a);
 void launch_wfinal(const LatDesc *desc, int nparts, int Rmax, int Tmax, const double *part, double *out,

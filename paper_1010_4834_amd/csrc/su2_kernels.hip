@@ -765,18 +765,16 @@ __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_r
 }
 
 // ---------------------------------------------------------------------------
-// Wilson loops (paper Sec. 2, W(R,T)).  Lines first: temporal lines
-// T(x;T) = U_4(x) .. U_4(x+(T-1)t) and spatial lines S_mu(x;R) =
+// Wilson loops (paper Sec. 2, W(R,T)).  Spatial lines first: S_mu(x;R) =
 // U_mu(x) .. U_mu(x+(R-1)mu), stored per site as Q<T> arrays
-//   tl[(T-1)*V + s], sl[(mu*Rmax + R-1)*V + s].
-// `sp` / `sp_raw`: the spatial links (smeared buffer or raw links).
+// sl[(mu*Rmax + R-1)*V + s].  `sp` / `sp_raw`: the spatial links (smeared
+// buffer or raw links).  Temporal lines are not stored: the trace kernel
+// builds them by transport from the raw temporal links.
 template <class T>
-__global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_raw, int Rmax, int Tmax,
-                                                Q<T> *tl, Q<T> *sl) {
+__global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_raw, int Rmax, Q<T> *sl) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tv = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tv.x);
-        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const Blocks<T, 3> Bs = blocks<T, 3>(sp, sp_raw ? d.off : d.soff, d.vh);
         const int s = tv.y + (int)threadIdx.x;
         const long long V = 2LL * d.vh;
@@ -785,17 +783,6 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
         udiv(r, d.n[0], d.inv_nx, r, c[0]);
         udiv(r, d.n[1], d.inv_ny, r, c[1]);
         udiv(r, d.n[2], d.inv_nz, c[3], c[2]);
-        {   // temporal lines
-            Q<T> P = qone<T>();
-            int t = c[3];
-            for (int TT = 1; TT <= Tmax; ++TT) {
-                const int y = s + (t - c[3]) * d.ns;
-                const int par = (c[0] + c[1] + c[2] + t) & 1;
-                P = qmul(P, lds_(B, 3, par, (uint32_t)y >> 1));
-                tl[(long long)(TT - 1) * V + s] = P;
-                t = (t + 1 == d.n[3]) ? 0 : t + 1;
-            }
-        }
 #pragma unroll
         for (int mu = 0; mu < 3; ++mu) {
             const int st = mu == 0 ? 1 : mu == 1 ? d.n[0] : d.n[0] * d.n[1];
@@ -812,14 +799,16 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
     });
 }
 
-// W(R,T) partials: blockIdx.y = R-1; per site and spatial mu,
-// 1/2 Tr[S(x;R) T(x+R mu;T) S(x+T t;R)^dag T(x;T)^dag]
-// = 1/2 Tr[(S(x;R) T(x+R mu;T)) (T(x;T) S(x+T t;R))^dag].  A workgroup walks
-// its share of the site tiles (a fixed assignment), each lane summing its
-// sites in binary64, then one compensated block sum per (R, workgroup, T).
+// W(R,T) partials: blockIdx.y = R-1; per site x and spatial mu the loop
+// 1/2 Tr[S(x;R) T(x+R mu;T) S(x+T t;R)^dag T(x;T)^dag] = 1/2 Tr[A_T S(x+T t;R)^dag]
+// with A_T = T(x;T)^dag S(x;R) T(x+R mu;T), built by transport up the two
+// temporal sides: A_0 = S(x;R), A_T = U_t(x+(T-1)t)^dag A_{T-1} U_t(x+R mu+(T-1)t).
+// Temporal links come from the raw link buffer (a quarter of the links),
+// the spatial lines from sl.  A workgroup walks its share of the site tiles
+// (a fixed assignment), each lane summing its sites in binary64, then one
+// compensated block sum per (R, workgroup, T).
 template <class T, int TMAX>
-__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, const Q<T> *tl, const Q<T> *sl,
-                                                double *part) {
+__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, const Q<T> *sl, double *part) {
     __shared__ DD lds[TMAX * 4];
     const int R = blockIdx.y + 1;
     double sum[TMAX];
@@ -828,6 +817,7 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, con
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tv = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tv.x);
+        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int s = tv.y + (int)threadIdx.x;
         const long long V = 2LL * d.vh;
         if (s < V) {
@@ -835,29 +825,35 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, con
             udiv(r, d.n[0], d.inv_nx, r, c[0]);
             udiv(r, d.n[1], d.inv_ny, r, c[1]);
             udiv(r, d.n[2], d.inv_nz, c[3], c[2]);
+            const Q<T> *slR = sl + (long long)(R - 1) * V;
+            const long long mstride = (long long)Rmax * V;
             int sR[3];
-            Q<T> S0[3];
+            Q<T> A[3];
 #pragma unroll
             for (int mu = 0; mu < 3; ++mu) {
                 const int st = mu == 0 ? 1 : mu == 1 ? d.n[0] : d.n[0] * d.n[1];
                 int cm = c[mu] + R;
                 if (cm >= d.n[mu]) cm -= d.n[mu];
                 sR[mu] = s + (cm - c[mu]) * st;
-                S0[mu] = sl[((long long)mu * Rmax + R - 1) * V + s];
+                A[mu] = slR[mu * mstride + s];
             }
+            // parity of x + k t and of x + R mu + k t (R flips it when odd)
+            const int p0 = (c[0] + c[1] + c[2] + c[3]) & 1, pR = p0 ^ (R & 1);
+            int ct = c[3];
 #pragma unroll
             for (int k = 0; k < TMAX; ++k) {
                 if (k < Tmax) {
-                    int ct = c[3] + k + 1;
-                    if (ct >= d.n[3]) ct -= d.n[3];
-                    const int sT = s + (ct - c[3]) * d.ns;
-                    const Q<T> t0 = tl[(long long)k * V + s];
+                    const int dt = (ct - c[3]) * d.ns;  // x + k t = s + dt
+                    const int pk = (p0 + k) & 1, pRk = (pR + k) & 1;
+                    const Q<T> ua = qdag(lds_(B, 3, pk, (uint32_t)(s + dt) >> 1));
+                    ct = (ct + 1 == d.n[3]) ? 0 : ct + 1;
+                    const int sT = s + (ct - c[3]) * d.ns;  // x + (k+1) t
                     double v = 0.0;
 #pragma unroll
                     for (int mu = 0; mu < 3; ++mu) {
-                        const Q<T> t1 = tl[(long long)k * V + sR[mu]];
-                        const Q<T> s2 = sl[((long long)mu * Rmax + R - 1) * V + sT];
-                        v += (double)half_tr_xyd(qmul(S0[mu], t1), qmul(t0, s2));
+                        const Q<T> ub = lds_(B, 3, pRk, (uint32_t)(sR[mu] + dt) >> 1);
+                        A[mu] = qmul(qmul(ua, A[mu]), ub);
+                        v += (double)half_tr_xyd(A[mu], slR[mu * mstride + sT]);
                     }
                     sum[k] += v;
                 }
@@ -1019,14 +1015,14 @@ void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *ds
     else hipLaunchKernelGGL((k_ape<double>), g, dim3(block), 0, s, a, src, src_raw, dst, alpha);
 }
 
-void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, int Tmax, void *tl,
-                   void *sl, int block, hipStream_t s) {
+void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, void *sl, int block,
+                   hipStream_t s) {
     if (f32)
-        hipLaunchKernelGGL((k_wlines<float>), grid_of(a, 0), dim3(block), 0, s, a, sp, sp_raw, Rmax, Tmax,
-                           (Q<float> *)tl, (Q<float> *)sl);
+        hipLaunchKernelGGL((k_wlines<float>), grid_of(a, 0), dim3(block), 0, s, a, sp, sp_raw, Rmax,
+                           (Q<float> *)sl);
     else
-        hipLaunchKernelGGL((k_wlines<double>), grid_of(a, 0), dim3(block), 0, s, a, sp, sp_raw, Rmax, Tmax,
-                           (Q<double> *)tl, (Q<double> *)sl);
+        hipLaunchKernelGGL((k_wlines<double>), grid_of(a, 0), dim3(block), 0, s, a, sp, sp_raw, Rmax,
+                           (Q<double> *)sl);
 }
 
 // `block` must be the site-tile size of the tile table: a workgroup sums
@@ -1038,21 +1034,20 @@ int wtrace_groups(const KArgs &a) {
 }
 
 template <class T>
-static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
-                            int block, hipStream_t s) {
+static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, const void *sl, double *part, int block,
+                            hipStream_t s) {
     dim3 g(wtrace_groups(a), (unsigned)Rmax), b((unsigned)block);
-    const Q<T> *t = (const Q<T> *)tl;
     const Q<T> *l = (const Q<T> *)sl;
-    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
-    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
-    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
-    else hipLaunchKernelGGL((k_wtrace<T, 32>), g, b, 0, s, a, Rmax, Tmax, t, l, part);
+    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4>), g, b, 0, s, a, Rmax, Tmax, l, part);
+    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8>), g, b, 0, s, a, Rmax, Tmax, l, part);
+    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16>), g, b, 0, s, a, Rmax, Tmax, l, part);
+    else hipLaunchKernelGGL((k_wtrace<T, 32>), g, b, 0, s, a, Rmax, Tmax, l, part);
 }
 
-void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *tl, const void *sl, double *part,
-                   int block, hipStream_t s) {
-    if (f32) launch_wtrace_t<float>(a, Rmax, Tmax, tl, sl, part, block, s);
-    else launch_wtrace_t<double>(a, Rmax, Tmax, tl, sl, part, block, s);
+void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *sl, double *part, int block,
+                   hipStream_t s) {
+    if (f32) launch_wtrace_t<float>(a, Rmax, Tmax, sl, part, block, s);
+    else launch_wtrace_t<double>(a, Rmax, Tmax, sl, part, block, s);
 }
 
 void launch_wfinal(const LatDesc *desc, int nparts, int Rmax, int Tmax, const double *part, double *out,
