@@ -1057,7 +1057,7 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     const bool sm = E->sm_cur >= 0;
     Timed t(E, SU2_K_WILSON, s);
     su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, E->wl_s, E->block, s);
-    su2::launch_wtrace(va, E->f32, Rmax, Tmax, E->wl_s, E->wpart, E->block, s);
+    su2::launch_wtrace(va, E->f32, Rmax, Tmax, V, d.n[3], E->wl_s, E->wpart, E->block, s);
     double *dout = nullptr;
     CHK(dalloc(E, &dout, sizeof(double) * Rmax * Tmax));
     su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout, s);

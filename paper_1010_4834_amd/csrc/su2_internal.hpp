@@ -61,8 +61,8 @@ void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *ds
                 int grid, hipStream_t s);
 void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, void *sl, int block,
                    hipStream_t s);
-void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *sl, double *part, int block,
-                   hipStream_t s);
+void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, long long V, int Nt, const void *sl, double *part,
+                   int block, hipStream_t s);
 // Workgroups per R of the Wilson-loop trace launch (its partials per R).
 int wtrace_groups(const KArgs &a);
 void launch_wfinal(const LatDesc *desc, int nparts, int Rmax, int Tmax, const double *part, double *out,

@@ -803,63 +803,75 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
 // 1/2 Tr[S(x;R) T(x+R mu;T) S(x+T t;R)^dag T(x;T)^dag] = 1/2 Tr[A_T S(x+T t;R)^dag]
 // with A_T = T(x;T)^dag S(x;R) T(x+R mu;T), built by transport up the two
 // temporal sides: A_0 = S(x;R), A_T = U_t(x+(T-1)t)^dag A_{T-1} U_t(x+R mu+(T-1)t).
-// Temporal links come from the raw link buffer (a quarter of the links),
-// the spatial lines from sl.  A workgroup walks its share of the site tiles
-// (a fixed assignment), each lane summing its sites in binary64, then one
-// compensated block sum per (R, workgroup, T).
-template <class T, int TMAX>
-__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, const Q<T> *sl, double *part) {
+// Temporal links come from the raw link buffer, the spatial lines from sl.
+//
+// A lane owns a column of NC sites x_j = x_0 + j t (j < NC; NC divides Nt)
+// of lattice 0 and takes the three directions mu one after another: at
+// temporal offset m from x_0 every column site with step k = m - j < Tmax
+// applies the same two temporal links and meets the same spatial line at
+// x_0 + (m+1) t, so each is loaded once per column instead of once per site
+// (NC + Tmax - 1 offsets of three loads per mu).  Column q = (spatial site
+// q % Ns, t block q / Ns); column tile i is columns [i B, (i+1) B) for block
+// size B.  A workgroup walks its share of the column tiles (a fixed
+// assignment), each lane summing in binary64, then one compensated block sum
+// per (R, workgroup, T).
+template <class T, int TMAX, int NC>
+__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, int ncols, int nctiles,
+                                                const Q<T> *sl, double *part) {
     __shared__ DD lds[TMAX * 4];
     const int R = blockIdx.y + 1;
     double sum[TMAX];
 #pragma unroll
     for (int k = 0; k < TMAX; ++k) sum[k] = 0.0;
-    for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tv = load_tile(a.tiles, tile);
-        const LatDesc d = load_desc(a.desc + tv.x);
-        const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
-        const int s = tv.y + (int)threadIdx.x;
-        const long long V = 2LL * d.vh;
-        if (s < V) {
-            int c[4], r = s;
-            udiv(r, d.n[0], d.inv_nx, r, c[0]);
-            udiv(r, d.n[1], d.inv_ny, r, c[1]);
-            udiv(r, d.n[2], d.inv_nz, c[3], c[2]);
-            const Q<T> *slR = sl + (long long)(R - 1) * V;
-            const long long mstride = (long long)Rmax * V;
-            int sR[3];
-            Q<T> A[3];
+    const LatDesc d = load_desc(a.desc);
+    const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
+    const long long V = 2LL * d.vh;
+    const Q<T> *slR = sl + (long long)(R - 1) * V;
+    const long long mstride = (long long)Rmax * V;
+    for (TileWalk w(nctiles, a.xcd_remap); w.ok(); w.next()) {
+        const int q = w.tile() * (int)blockDim.x + (int)threadIdx.x;
+        if (q >= ncols) continue;
+        // q = sp + Ns tb: spatial site sp = x + Nx (y + Ny z), t0 = NC tb
+        int c[3], r, tb, sp;
+        udiv(q, d.n[0], d.inv_nx, r, c[0]);
+        udiv(r, d.n[1], d.inv_ny, r, c[1]);
+        udiv(r, d.n[2], d.inv_nz, tb, c[2]);
+        sp = q - tb * d.ns;
+        const int t0 = NC * tb;
+        const int s0 = sp + t0 * d.ns;  // site of x_0
 #pragma unroll
-            for (int mu = 0; mu < 3; ++mu) {
-                const int st = mu == 0 ? 1 : mu == 1 ? d.n[0] : d.n[0] * d.n[1];
-                int cm = c[mu] + R;
-                if (cm >= d.n[mu]) cm -= d.n[mu];
-                sR[mu] = s + (cm - c[mu]) * st;
-                A[mu] = slR[mu * mstride + s];
-            }
-            // parity of x + k t and of x + R mu + k t (R flips it when odd)
-            const int p0 = (c[0] + c[1] + c[2] + c[3]) & 1, pR = p0 ^ (R & 1);
-            int ct = c[3];
+        for (int mu = 0; mu < 3; ++mu) {
+            const int st = mu == 0 ? 1 : mu == 1 ? d.n[0] : d.n[0] * d.n[1];
+            int cm = c[mu] + R;
+            if (cm >= d.n[mu]) cm -= d.n[mu];
+            const int sR = s0 + (cm - c[mu]) * st;  // x_0 + R mu
+            Q<T> A[NC];
 #pragma unroll
-            for (int k = 0; k < TMAX; ++k) {
-                if (k < Tmax) {
-                    const int dt = (ct - c[3]) * d.ns;  // x + k t = s + dt
-                    const int pk = (p0 + k) & 1, pRk = (pR + k) & 1;
-                    const Q<T> ua = qdag(lds_(B, 3, pk, (uint32_t)(s + dt) >> 1));
-                    ct = (ct + 1 == d.n[3]) ? 0 : ct + 1;
-                    const int sT = s + (ct - c[3]) * d.ns;  // x + (k+1) t
-                    double v = 0.0;
+            for (int j = 0; j < NC; ++j) A[j] = slR[mu * mstride + s0 + j * d.ns];
+            // parity of x_0 + m t and of x_0 + R mu + m t (R flips it when odd)
+            const int p0 = (c[0] + c[1] + c[2] + t0) & 1, pR = p0 ^ (R & 1);
+            int tm = t0;  // t of x_0 + m t
 #pragma unroll
-                    for (int mu = 0; mu < 3; ++mu) {
-                        const Q<T> ub = lds_(B, 3, pRk, (uint32_t)(sR[mu] + dt) >> 1);
-                        A[mu] = qmul(qmul(ua, A[mu]), ub);
-                        v += (double)half_tr_xyd(A[mu], slR[mu * mstride + sT]);
+            for (int m = 0; m < NC + TMAX - 1; ++m) {
+                if (m < NC + Tmax - 1) {
+                    const int dt = (tm - t0) * d.ns;  // x_0 + m t = s0 + dt
+                    const int pm = (p0 + m) & 1, pRm = (pR + m) & 1;
+                    const Q<T> ua = qdag(lds_(B, 3, pm, (uint32_t)(s0 + dt) >> 1));
+                    const Q<T> ub = lds_(B, 3, pRm, (uint32_t)(sR + dt) >> 1);
+                    tm = (tm + 1 == d.n[3]) ? 0 : tm + 1;
+                    const Q<T> top = slR[mu * mstride + s0 + (tm - t0) * d.ns];  // S(x_0 + (m+1) t; R)
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) {
+                        const int k = m - j;
+                        if (k >= 0 && k < TMAX && k < Tmax) {
+                            A[j] = qmul(qmul(ua, A[j]), ub);
+                            sum[k] += (double)half_tr_xyd(A[j], top);
+                        }
                     }
-                    sum[k] += v;
                 }
             }
         }
-    });
+    }
     DD acc[TMAX];
 #pragma unroll
     for (int k = 0; k < TMAX; ++k) acc[k] = DD{sum[k], 0.0};
@@ -1033,21 +1045,38 @@ int wtrace_groups(const KArgs &a) {
     return g < 1024 ? (g < 8 ? 8 : g) : 1024;
 }
 
-template <class T>
-static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, const void *sl, double *part, int block,
-                            hipStream_t s) {
-    dim3 g(wtrace_groups(a), (unsigned)Rmax), b((unsigned)block);
-    const Q<T> *l = (const Q<T> *)sl;
-    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4>), g, b, 0, s, a, Rmax, Tmax, l, part);
-    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8>), g, b, 0, s, a, Rmax, Tmax, l, part);
-    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16>), g, b, 0, s, a, Rmax, Tmax, l, part);
-    else hipLaunchKernelGGL((k_wtrace<T, 32>), g, b, 0, s, a, Rmax, Tmax, l, part);
+// Column height of the Wilson trace: 4 when it divides Nt (binary32, up to
+// 16 time steps: more would spill registers), else 2 (extents are even).
+template <class T> static int wtrace_nc(int Nt, int Tmax) {
+    return (sizeof(T) == 4 && Nt % 4 == 0 && Tmax <= 16) ? 4 : 2;
 }
 
-void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, const void *sl, double *part, int block,
-                   hipStream_t s) {
-    if (f32) launch_wtrace_t<float>(a, Rmax, Tmax, sl, part, block, s);
-    else launch_wtrace_t<double>(a, Rmax, Tmax, sl, part, block, s);
+template <class T, int NC>
+static void launch_wtrace_nc(const KArgs &a, int Rmax, int Tmax, long long V, const void *sl, double *part,
+                             int block, hipStream_t s) {
+    const dim3 g(wtrace_groups(a), (unsigned)Rmax), b((unsigned)block);
+    const int ncols = (int)(V / NC), nct = (ncols + block - 1) / block;
+    const Q<T> *l = (const Q<T> *)sl;
+    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+    else if constexpr (NC == 2) hipLaunchKernelGGL((k_wtrace<T, 32, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+}
+
+template <class T>
+static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, long long V, int Nt, const void *sl, double *part,
+                            int block, hipStream_t s) {
+    const int nc = wtrace_nc<T>(Nt, Tmax);
+    if constexpr (sizeof(T) == 4) {
+        if (nc == 4) return launch_wtrace_nc<T, 4>(a, Rmax, Tmax, V, sl, part, block, s);
+    }
+    launch_wtrace_nc<T, 2>(a, Rmax, Tmax, V, sl, part, block, s);
+}
+
+void launch_wtrace(const KArgs &a, bool f32, int Rmax, int Tmax, long long V, int Nt, const void *sl, double *part,
+                   int block, hipStream_t s) {
+    if (f32) launch_wtrace_t<float>(a, Rmax, Tmax, V, Nt, sl, part, block, s);
+    else launch_wtrace_t<double>(a, Rmax, Tmax, V, Nt, sl, part, block, s);
 }
 
 void launch_wfinal(const LatDesc *desc, int nparts, int Rmax, int Tmax, const double *part, double *out,

@@ -81,6 +81,25 @@ def test_measurements_any_launch_shape(su2, orc, launch):
     lat.close()
 
 
+@pytest.mark.parametrize("dims,Rm,Tm", [
+    ((4, 2, 2, 20), 2, 18),   # more than 16 time steps (column height 2)
+    ((2, 2, 4, 8), 2, 8),     # T = Nt: the temporal transport wraps the full period
+    ((2, 4, 2, 12), 2, 12),   # column height 4 in binary32 (Nt divisible by 4)
+])
+def test_wilson_columns_and_long_times(su2, orc, dims, Rm, Tm):
+    """The trace kernel takes columns of sites along t and transports the
+    temporal sides; long T, a full temporal wrap and both column heights
+    against the oracle."""
+    U = inputs.random_config(dims, 44)
+    U32 = U.astype(np.float32).astype(np.float64)
+    for prec, ref, tw in ((su2.F64, U, 1e-13), (su2.F32, U32, 2e-5)):
+        lat = su2.Lattice(dims, start=su2.COLD, prec=prec)
+        lat.set_links(ref)
+        W = lat.wilson_loops(Rm, Tm)
+        assert np.abs(W - orc.wilson(dims, ref, Rm, Tm)).max() < tw, prec
+        lat.close()
+
+
 def test_c4_full_size_sampled(su2, orc):
     """24^3 x 48, beta = 2.5, hot start seed 4: APE alpha = 0.7 x 25 on the
     spatial links, W(R <= 12, T <= 16); sampled (R, T) against the oracle."""
