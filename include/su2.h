@@ -146,8 +146,11 @@ su2_status su2_ape_smear(su2_lattice lat, double alpha, int nsteps);
 /* On-axis Wilson loops (paper Sec. 2, W(R,T)): out[(R-1)*Tmax + (T-1)] for
  * 1 <= R <= Rmax, 1 <= T <= Tmax, half trace averaged over all sites and the
  * three spatial directions.  Spatial lines use the smeared links when
- * su2_ape_smear produced them since the last update, else the raw links.
- * Rmax <= min(Nx,Ny,Nz), Tmax <= min(Nt, 32), else EINVAL.  Synchronises. */
+ * su2_ape_smear produced them since the last update, else the raw links;
+ * the temporal sides always use the raw links.  The handle keeps a device
+ * buffer of 3*Rmax*V spatial-line quaternions (grown on demand, freed with
+ * the handle).  Rmax <= min(Nx,Ny,Nz), Tmax <= min(Nt, 32), else EINVAL.
+ * Synchronises. */
 su2_status su2_wilson_loops(su2_lattice lat, int Rmax, int Tmax, double *out);
 
 /* Copy links to / from a host array in the canonical layout (V*16 float64).
