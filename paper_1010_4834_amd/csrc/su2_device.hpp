@@ -104,9 +104,6 @@ __device__ __forceinline__ void qmul_acc(Q<T> &s, const Q<T> &x, const Q<T> &y) 
 template <class T> __device__ __forceinline__ Q<T> qdag(const Q<T> &x) {
     return Q<T>{x.a, -x.b, -x.c, -x.d};
 }
-template <class T> __device__ __forceinline__ void qacc(Q<T> &s, const Q<T> &x) {
-    s.a += x.a; s.b += x.b; s.c += x.c; s.d += x.d;
-}
 // 1/2 Re Tr(x y^dag) = x0 y0 + x.y
 template <class T> __device__ __forceinline__ T half_tr_xyd(const Q<T> &x, const Q<T> &y) {
     return x.a * y.a + x.b * y.b + x.c * y.c + x.d * y.d;

@@ -738,14 +738,22 @@ __device__ __forceinline__ void ape_link(const LatDesc &d, const Blocks<T, 3> &B
         const Q<T> b1 = lds_(Bs, nu, op, (uint32_t)(S.s + bn) >> 1);
         const Q<T> b2 = lds_(Bs, MU, op, (uint32_t)(S.s + bn) >> 1);
         const Q<T> b3 = lds_(Bs, nu, par, (uint32_t)(s_mu + bn) >> 1);
-        qacc(sum, qmul(qmul(a1, a2), qdag(a3)));
-        qacc(sum, qmul(qmul(qdag(b1), b2), b3));
+        qmul_acc(sum, qmul(a1, a2), qdag(a3));
+        qmul_acc(sum, qmul(qdag(b1), b2), b3);
     }
     const Q<T> u = lds_(Bs, MU, par, (uint32_t)cb);
     const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
     const Q<T> w{w0 * u.a + w1 * sum.a, w0 * u.b + w1 * sum.b, w0 * u.c + w1 * sum.c, w0 * u.d + w1 * sum.d};
-    const double n2 = (double)w.a * w.a + (double)w.b * w.b + (double)w.c * w.c + (double)w.d * w.d;
-    sts_(Bd, MU, par, (uint32_t)cb, n2 > 0.0 ? qnormalize(w) : u);
+    // projection onto SU(2): scale by the binary64 1/|w| (a smeared sum is
+    // in general far from unit norm, so no near-group shortcut)
+    const double wa = w.a, wb = w.b, wc = w.c, wd = w.d;
+    const double n2 = wa * wa + wb * wb + wc * wc + wd * wd;
+    Q<T> un = u;
+    if (n2 > 0.0) {
+        const double f = 1.0 / sqrt(n2);
+        un = Q<T>{(T)(wa * f), (T)(wb * f), (T)(wc * f), (T)(wd * f)};
+    }
+    sts_(Bd, MU, par, (uint32_t)cb, un);
 }
 
 template <class T>
@@ -1037,9 +1045,8 @@ void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rma
                            (Q<double> *)sl);
 }
 
-// `block` must be the site-tile size of the tile table: a workgroup sums
-// exactly the sites of its tiles.  Workgroups per R: enough to fill the
-// chip a few times over, each taking several tiles (a multiple of 8).
+// Workgroups per R of the Wilson trace: enough to fill the chip a few times
+// over, each taking several column tiles (a multiple of 8, one share per XCD).
 int wtrace_groups(const KArgs &a) {
     const int g = ((a.ntiles + 7) / 8) * 8;
     return g < 1024 ? (g < 8 ? 8 : g) : 1024;
