@@ -71,6 +71,9 @@ def configs():
         "c5": dict(dims=c5[0], betas=c5[1], seed=5, poly=True,
                    desc="64 uneven lattices L^3xNt, L in {8,12,16,24}, Nt in {4,6,8,L}, "
                         "beta in [2.2,2.8], 1 sweep + plaquette + Polyakov per step"),
+        "c1": dict(dims=[(8, 8, 8, 8)], betas=[2.3], seed=1, poly=False,
+                   desc="8^4 SU(2) heat bath, beta=2.3, cold start, binary64, 20 sweeps with the "
+                        "plaquette after each (launch-bound; context)"),
         "c4": dict(dims=[(24, 24, 24, 48)], betas=[2.5], seed=4, poly=False,
                    desc="24^3x48, beta=2.5: per configuration 5 heat-bath sweeps, APE smearing "
                         "(alpha 0.7, 25 steps) of the spatial links and on-axis Wilson loops "
@@ -109,6 +112,66 @@ def copy_probe(torch):
     gbs = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del x, y
     return gbs
+
+
+def bench_c1(su2, args, cfg, stream):
+    """8^4 binary64 from a cold start: 20 sweeps, plaquette after each, as
+    plain per-call API use (one sweep call and one synchronising plaquette
+    call per sweep) and as one graph-replayed ensemble series."""
+    import numpy as np
+    import torch
+    dims, beta, seed = cfg["dims"][0], cfg["betas"][0], cfg["seed"]
+    nsw = 20
+    updates = 4 * int(np.prod(dims)) * nsw
+
+    def plain():
+        lat = su2.su2_create(*dims, su2.COLD, seed, su2.F64)
+        su2.su2_set_stream(lat, stream.cuda_stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = []
+        for _ in range(nsw):
+            su2.su2_heatbath(lat, beta, 1, seed)
+            P.append(su2.su2_plaquette(lat)[0])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        su2.su2_set_timing(lat, 1)
+        su2.su2_heatbath(lat, beta, nsw, seed)
+        hb_ms, hb_n = su2.su2_get_timing(lat, su2.K_HEATBATH)
+        su2.su2_destroy(lat)
+        return P, dt, 1e3 * hb_ms / hb_n
+
+    def graph():
+        # the first run (graph capture included) gives the cold-start series;
+        # the second, continuing the chain, is timed
+        ens = su2.su2_ensemble_create([dims], [beta], su2.COLD, seed, su2.F64)
+        su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
+        P, _ = su2.su2_ensemble_run(ens, 1, nsw, seed, True, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su2.su2_ensemble_run(ens, 1, nsw, seed, True, False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        su2.su2_ensemble_destroy(ens)
+        return P[0], dt
+
+    for _ in range(max(args.warmup, 1)):   # warm-up on throwaway lattices
+        plain()
+        graph()
+    P, t_plain, hb_us = plain()
+    Pg, t_graph = graph()
+    return {
+        "metric": "heat-bath link updates/s, 8^4 binary64 (launch-bound context)",
+        "value": updates / t_graph, "unit": "link updates/s", "n_gpus": 1, "steps": nsw,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_graph / nsw, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic (cold start)",
+        "config": {"workload": cfg["desc"], "sites": int(np.prod(dims))},
+        "plain_calls": {"value": updates / t_plain, "ms_per_step": 1e3 * t_plain / nsw,
+                        "form": "su2_heatbath + su2_plaquette per sweep (synchronising)"},
+        "hb_avg_launch_us": hb_us,
+        "plaquettes": P,
+        "graph_vs_plain_max_abs_dP": float(np.abs(np.asarray(Pg) - np.asarray(P)).max()),
+    }
 
 
 def bench_c4(su2, args, cfg, stream):
@@ -219,6 +282,9 @@ def main():
     stream = torch.cuda.Stream()
     if args.config == "c4":
         print(json.dumps(bench_c4(su2, args, cfg, stream)), flush=True)
+        return
+    if args.config == "c1":
+        print(json.dumps(bench_c1(su2, args, cfg, stream)), flush=True)
         return
 
     ens = su2.su2_ensemble_create(dims, betas, su2.HOT, seed, su2.F32)

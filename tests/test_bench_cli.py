@@ -1,0 +1,27 @@
+"""bench.py's command-line contract on the host (no GPU work is started)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_workload_configs():
+    sys.path.insert(0, ROOT)
+    import bench
+    cfg = bench.configs()
+    assert set(cfg) == {"c1", "c2", "c3", "c4", "c5", "control64"}
+    assert cfg["c2"]["dims"] == [(32, 32, 32, 32)] and cfg["c2"]["betas"] == [2.6]
+    assert cfg["c1"]["dims"] == [(8, 8, 8, 8)] and cfg["c1"]["seed"] == 1
+    assert len(cfg["c3"]["dims"]) == 16 and len(cfg["c5"]["dims"]) == 64
+    for c in cfg.values():
+        assert all(all(n % 2 == 0 for n in d) for d in c["dims"])
