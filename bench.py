@@ -207,7 +207,17 @@ def bench_c4(su2, args, cfg, stream):
         one_config()
     t = {k: su2.su2_get_timing(lat.h, getattr(su2, k)) for k in ("K_HEATBATH", "K_APE", "K_WILSON")}
     su2.su2_set_timing(lat.h, 0)
+    # binary32 error of APE + Wilson loops: the same configuration (its
+    # binary32 link values) smeared and measured in binary64
+    U = lat.get_links()
+    W32 = np.asarray(lat.wilson_loops(12, 16)).reshape(12, 16)
     lat.close()
+    lat64 = su2.Lattice(dims, start=su2.COLD, prec=su2.F64, stream=stream.cuda_stream)
+    lat64.set_links(U)
+    lat64.ape_smear(0.7, 25)
+    W64 = np.asarray(lat64.wilson_loops(12, 16)).reshape(12, 16)
+    lat64.close()
+    err = np.abs(W32 - W64)
     ms = {k: v[0] / nconf for k, v in t.items()}
     ape_step_us = 1e3 * t["K_APE"][0] / max(t["K_APE"][1], 1)
     ape_bytes = 6 * V * 16   # 3V spatial links read, 3V written per step
@@ -223,6 +233,10 @@ def bench_c4(su2, args, cfg, stream):
         "ape_step": {"avg_launch_us": ape_step_us, "bytes_per_launch": ape_bytes,
                      "GBs": ape_bytes / (ape_step_us * 1e-6) / 1e9},
         "W_1_1": float(W[0]),
+        "fp32_error": {"max_abs": float(err.max()),
+                       "max_rel": float((err / np.abs(W64)).max()),
+                       "abs_by_T_at_R12": err[11].tolist(),
+                       "form": "binary32 APE + Wilson loops vs binary64 on the same configuration"},
     }
 
 
