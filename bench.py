@@ -96,22 +96,20 @@ def cpu_baseline(dims, beta, seed, nsweeps):
     return 4 * V * nsweeps / dt, dt
 
 
-def copy_probe(torch):
-    """Device-to-device copy of 1 GiB: the achievable streaming bandwidth."""
-    x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(5):
-        y.copy_(x)
-    c1.record()
-    torch.cuda.synchronize()
-    gbs = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
-    del x, y
-    return gbs
+def cpu_all_cores(dims, beta, nsweeps, nthreads):
+    """The same oracle on nthreads host threads at once, each on its own
+    lattice (seeds 2, 3, ...).  The oracle is a C library called through
+    ctypes, which releases the interpreter lock for each call, so the threads
+    run in parallel; no process is started.  Aggregate link updates/s over
+    the slowest thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(nthreads) as ex:
+        res = list(ex.map(lambda i: cpu_baseline(dims, beta, 2 + i, nsweeps), range(nthreads)))
+    V = 1
+    for d in dims:
+        V *= d
+    slowest = max(dt for _, dt in res)
+    return 4 * V * nsweeps * nthreads / slowest, slowest
 
 
 def bench_c1(su2, args, cfg, stream):
@@ -274,7 +272,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="run the 1 GiB device copy also for configurations other than c2")
     ap.add_argument("--no-copy-probe", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--cpu-sweeps", type=int, default=8)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads for the all-core oracle figure (0: min(16, cores))")
     ap.add_argument("--launch", default=None,
                     help="block,grid,xcd_remap,links_per_lane (skips tuning)")
     args = ap.parse_args()
@@ -414,6 +414,12 @@ def main():
                                "sample": f"{args.cpu_sweeps} heat-bath sweeps + plaquette of the "
                                          f"32^4 beta=2.6 hot-start lattice, serial FP64 oracle, "
                                          f"{dt:.1f} s"}
+        nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
+        if nthr > 1:
+            agg, dt = cpu_all_cores(dims[0], betas[0], 2, nthr)
+            out["cpu_all_cores"] = {"value": agg, "unit": "link updates/s", "cores": nthr, "kind": "oracle",
+                                    "sample": f"{nthr} host threads at once, each 2 sweeps + plaquette of "
+                                              f"its own 32^4 lattice, serial FP64 oracle, {dt:.1f} s"}
     print(json.dumps(out), flush=True)
 
 
