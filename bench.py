@@ -96,6 +96,25 @@ def cpu_baseline(dims, beta, seed, nsweeps):
     return 4 * V * nsweeps / dt, dt
 
 
+def host_info():
+    """CPU model and thread count of the host that timed the oracle."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from oracle import build as ob
+        flags = "gcc " + " ".join(ob.FLAGS)
+    except Exception:
+        flags = None
+    return {"cpu": model, "threads": os.cpu_count(), "oracle_build": flags}
+
+
 def cpu_all_cores(dims, beta, nsweeps, nthreads):
     """The same oracle on nthreads host threads at once, each on its own
     lattice (seeds 2, 3, ...).  The oracle is a C library called through
@@ -414,6 +433,7 @@ def main():
                                "sample": f"{args.cpu_sweeps} heat-bath sweeps + plaquette of the "
                                          f"32^4 beta=2.6 hot-start lattice, serial FP64 oracle, "
                                          f"{dt:.1f} s"}
+        out["host"] = host_info()
         nthr = args.cpu_threads or min(16, os.cpu_count() or 1)
         if nthr > 1:
             agg, dt = cpu_all_cores(dims[0], betas[0], 2, nthr)
