@@ -96,6 +96,24 @@ def cpu_baseline(dims, beta, seed, nsweeps):
     return 4 * V * nsweeps / dt, dt
 
 
+def copy_probe(torch):
+    """Device-to-device copy of 1 GiB: the achievable streaming bandwidth."""
+    x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        y.copy_(x)
+    c1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del x, y
+    return gbs
+
+
 def host_info():
     """CPU model and thread count of the host that timed the oracle."""
     model = None

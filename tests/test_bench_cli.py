@@ -25,3 +25,26 @@ def test_workload_configs():
     assert len(cfg["c3"]["dims"]) == 16 and len(cfg["c5"]["dims"]) == 64
     for c in cfg.values():
         assert all(all(n % 2 == 0 for n in d) for d in c["dims"])
+
+
+def test_every_global_name_is_defined():
+    """Every name that a function of bench.py reads as a global exists at
+    module level or among the builtins (a renamed or deleted helper fails
+    here rather than on the GPU)."""
+    import builtins
+    import symtable
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    top = symtable.symtable(src, "bench.py", "exec")
+    defined = {s.get_name() for s in top.get_symbols() if s.is_assigned() or s.is_imported()}
+    defined |= set(dir(builtins))
+    missing = []
+
+    def walk(t):
+        for child in t.get_children():
+            if child.get_type() == "function":
+                for s in child.get_symbols():
+                    if s.is_global() and s.is_referenced() and s.get_name() not in defined:
+                        missing.append((child.get_name(), s.get_name()))
+            walk(child)
+    walk(top)
+    assert not missing, missing
