@@ -28,6 +28,10 @@ using su2::Tile;
 namespace {
 
 constexpr int NMEAS_GRAPHS = 4;  // measurement mask 0..3 (bit 0 plaquette, bit 1 Polyakov)
+// Sweeps per captured multi-sweep graph.  Each graph launch leaves the GPU
+// idle for ~8 us before its first kernel (measured), so long runs replay a
+// graph of several sweeps and pay that once per GRAPH_SWEEPS sweeps.
+constexpr int GRAPH_SWEEPS = 16;
 constexpr long long MAX_SITES = 1LL << 30;
 
 struct EventPair {
@@ -75,7 +79,8 @@ struct su2_ensemble_s {
     int ser_cap = 0;
 
     hipStream_t own = nullptr, user = nullptr;
-    hipGraphExec_t gexec[NMEAS_GRAPHS] = {};
+    hipGraphExec_t gexec[NMEAS_GRAPHS] = {};   // one sweep
+    hipGraphExec_t gexecn[NMEAS_GRAPHS] = {};  // GRAPH_SWEEPS sweeps
 
     void *sm[2] = {nullptr, nullptr};
     int sm_cur = -1;  // index of the valid smeared buffer, -1 none
@@ -180,11 +185,12 @@ KArgs kargs(su2_ensemble_s *E, int which = 0) {
 }
 
 void drop_graphs(su2_ensemble_s *E) {
-    for (auto &g : E->gexec)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (auto *set : {E->gexec, E->gexecn})
+        for (int i = 0; i < NMEAS_GRAPHS; ++i)
+            if (set[i]) {
+                (void)hipGraphExecDestroy(set[i]);
+                set[i] = nullptr;
+            }
 }
 
 // ---- per-kernel event timing -------------------------------------------
@@ -466,26 +472,38 @@ su2_status series_batch(su2_ensemble_s *E, int meas, unsigned first, int nsw, hi
     return SU2_OK;
 }
 
+// Capture `count` consecutive sweeps into one executable graph.
+su2_status capture_sweeps(su2_ensemble_s *E, int meas, int count, hipGraphExec_t *out) {
+    HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
+    su2_status st = SU2_OK;
+    for (int k = 0; k < count && st == SU2_OK; ++k) st = enqueue_sweep(E, meas, E->own);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(E->own, &g);
+    if (st != SU2_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCHK(e);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    return SU2_OK;
+}
+
 su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas) {
     hipStream_t s = E->stream();
     const bool use_graph = !E->timing && nsweeps > 1 && !std::getenv("SU2_NO_GRAPH");
-    if (use_graph && !E->gexec[meas]) {
-        hipGraph_t g = nullptr;
-        HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
-        su2_status st = enqueue_sweep(E, meas, E->own);
-        hipGraph_t gg = nullptr;
-        hipError_t e = hipStreamEndCapture(E->own, &gg);
-        if (st != SU2_OK) return st;
-        HIPCHK(e);
-        g = gg;
-        HIPCHK(hipGraphInstantiate(&E->gexec[meas], g, nullptr, nullptr, 0));
-        HIPCHK(hipGraphDestroy(g));
-    }
     // batches of at most nslots sweeps between series reductions
     const int batch = meas ? E->nslots : nsweeps;
+    const bool multi = use_graph && std::min(batch, nsweeps) >= GRAPH_SWEEPS;
+    if (use_graph && !E->gexec[meas]) CHK(capture_sweeps(E, meas, 1, &E->gexec[meas]));
+    if (multi && !E->gexecn[meas]) CHK(capture_sweeps(E, meas, GRAPH_SWEEPS, &E->gexecn[meas]));
     for (int done = 0; done < nsweeps; done += batch) {
         const int b = std::min(batch, nsweeps - done);
-        for (int k = 0; k < b; ++k) {
+        int k = 0;
+        if (multi)
+            for (; k + GRAPH_SWEEPS <= b; k += GRAPH_SWEEPS) HIPCHK(hipGraphLaunch(E->gexecn[meas], s));
+        for (; k < b; ++k) {
             if (use_graph) HIPCHK(hipGraphLaunch(E->gexec[meas], s));
             else CHK(enqueue_sweep(E, meas, s));
         }
