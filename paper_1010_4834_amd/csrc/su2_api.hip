@@ -28,10 +28,18 @@ using su2::Tile;
 namespace {
 
 constexpr int NMEAS_GRAPHS = 4;  // measurement mask 0..3 (bit 0 plaquette, bit 1 Polyakov)
-// Sweeps per captured multi-sweep graph.  Each graph launch leaves the GPU
-// idle for ~8 us before its first kernel (measured), so long runs replay a
-// graph of several sweeps and pay that once per GRAPH_SWEEPS sweeps.
-constexpr int GRAPH_SWEEPS = 16;
+// Sweeps per captured multi-sweep graph (SU2_GRAPH_SWEEPS overrides; 0 or 1
+// replays single-sweep graphs only).  Each graph launch leaves the GPU idle
+// for ~8 us before its first kernel (measured), so long runs replay a graph
+// of several sweeps and pay that once per graph.
+constexpr int GRAPH_SWEEPS_DEFAULT = 16;
+int graph_sweeps() {
+    static const int n = [] {
+        const char *e = std::getenv("SU2_GRAPH_SWEEPS");
+        return e ? std::max(0, std::min(4096, std::atoi(e))) : GRAPH_SWEEPS_DEFAULT;
+    }();
+    return n;
+}
 constexpr long long MAX_SITES = 1LL << 30;
 
 struct EventPair {
@@ -80,7 +88,7 @@ struct su2_ensemble_s {
 
     hipStream_t own = nullptr, user = nullptr;
     hipGraphExec_t gexec[NMEAS_GRAPHS] = {};   // one sweep
-    hipGraphExec_t gexecn[NMEAS_GRAPHS] = {};  // GRAPH_SWEEPS sweeps
+    hipGraphExec_t gexecn[NMEAS_GRAPHS] = {};  // graph_sweeps() sweeps
 
     void *sm[2] = {nullptr, nullptr};
     int sm_cur = -1;  // index of the valid smeared buffer, -1 none
@@ -495,14 +503,15 @@ su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas) {
     const bool use_graph = !E->timing && nsweeps > 1 && !std::getenv("SU2_NO_GRAPH");
     // batches of at most nslots sweeps between series reductions
     const int batch = meas ? E->nslots : nsweeps;
-    const bool multi = use_graph && std::min(batch, nsweeps) >= GRAPH_SWEEPS;
+    const int gs = graph_sweeps();
+    const bool multi = use_graph && gs > 1 && std::min(batch, nsweeps) >= gs;
     if (use_graph && !E->gexec[meas]) CHK(capture_sweeps(E, meas, 1, &E->gexec[meas]));
-    if (multi && !E->gexecn[meas]) CHK(capture_sweeps(E, meas, GRAPH_SWEEPS, &E->gexecn[meas]));
+    if (multi && !E->gexecn[meas]) CHK(capture_sweeps(E, meas, gs, &E->gexecn[meas]));
     for (int done = 0; done < nsweeps; done += batch) {
         const int b = std::min(batch, nsweeps - done);
         int k = 0;
         if (multi)
-            for (; k + GRAPH_SWEEPS <= b; k += GRAPH_SWEEPS) HIPCHK(hipGraphLaunch(E->gexecn[meas], s));
+            for (; k + gs <= b; k += gs) HIPCHK(hipGraphLaunch(E->gexecn[meas], s));
         for (; k < b; ++k) {
             if (use_graph) HIPCHK(hipGraphLaunch(E->gexec[meas], s));
             else CHK(enqueue_sweep(E, meas, s));
