@@ -31,8 +31,9 @@ constexpr int NMEAS_GRAPHS = 4;  // measurement mask 0..3 (bit 0 plaquette, bit 
 // Sweeps per captured multi-sweep graph (SU2_GRAPH_SWEEPS overrides; 0 or 1
 // replays single-sweep graphs only).  Each graph launch leaves the GPU idle
 // for ~8 us before its first kernel (measured), so long runs replay a graph
-// of several sweeps and pay that once per graph.
-constexpr int GRAPH_SWEEPS_DEFAULT = 16;
+// of several sweeps and pay that once per graph.  Measured at 32^4: 8 sweeps
+// per graph beat 16, 32 and 64 (the per-launch cost grows with graph size).
+constexpr int GRAPH_SWEEPS_DEFAULT = 8;
 int graph_sweeps() {
     static const int n = [] {
         const char *e = std::getenv("SU2_GRAPH_SWEEPS");
