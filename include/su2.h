@@ -222,11 +222,13 @@ su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
 /* nsweeps heat-bath sweeps of every lattice at its own beta, with the mean
  * plaquette and Polyakov loop of every lattice after every sweep written to
  * plaq[i*nsweeps + k] and poly[i*nsweeps + k] (either may be NULL to skip
- * that measurement).  One sweep (eight substep launches; the plaquette is
- * summed inside the odd substeps) is captured once in a HIP graph and
- * replayed; per-sweep partial sums are reduced once per batch of up to 512
- * sweeps, and the series stay on the device until the end.  Measuring does
- * not change the Markov chain. */
+ * that measurement).  A sweep (eight substep launches; the plaquette is
+ * summed inside the odd substeps) is captured in HIP graphs of one and of
+ * several sweeps (8; environment SU2_GRAPH_SWEEPS) that are replayed;
+ * per-sweep partial sums are reduced once per batch of up to 512 sweeps,
+ * and the series stay on the device until the end.  Measuring does not
+ * change the Markov chain.  Environment SU2_NO_GRAPH launches every kernel
+ * directly. */
 su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, uint64_t seed, double *plaq,
                             double *poly);
 su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
