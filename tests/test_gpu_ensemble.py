@@ -106,3 +106,29 @@ def test_measuring_does_not_change_the_chain(su2, prec):
     assert np.array_equal(a.get_links(0), b.get_links())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_multi_sweep_graphs_match_direct_launches(su2, prec):
+    """21 sweeps replay two graphs of 8 sweeps and five single-sweep graphs;
+    links, plaquette and Polyakov series are bit for bit those of the same
+    sweeps launched one kernel at a time (SU2_NO_GRAPH)."""
+    import os
+    dims, betas = [(6, 4, 10, 6), (4, 4, 4, 8)], [2.3, 2.6]
+    out = []
+    for direct in (False, True):
+        if direct:
+            os.environ["SU2_NO_GRAPH"] = "1"
+        try:
+            ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=9, prec=getattr(su2, prec))
+            P, L = ens.run(21, 9)
+            P2, L2 = ens.run(5, 9)     # the counter continues across runs
+            out.append((P, L, P2, L2, [ens.get_links(i) for i in range(len(dims))]))
+            ens.close()
+        finally:
+            os.environ.pop("SU2_NO_GRAPH", None)
+    (a, b) = out
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    for x, y in zip(a[4], b[4]):
+        assert np.array_equal(x, y)
