@@ -175,6 +175,28 @@ su2_status dalloc(su2_ensemble_s *E, P **p, size_t bytes) {
     return SU2_OK;
 }
 
+// A device buffer or event pair owned by one call, released on every return
+// path (errors included).
+template <class P> struct TmpDev {
+    P *p = nullptr;
+    TmpDev() = default;
+    TmpDev(const TmpDev &) = delete;
+    TmpDev &operator=(const TmpDev &) = delete;
+    ~TmpDev() {
+        if (p) (void)hipFree(p);
+    }
+};
+struct TmpEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+    TmpEvents() = default;
+    TmpEvents(const TmpEvents &) = delete;
+    TmpEvents &operator=(const TmpEvents &) = delete;
+    ~TmpEvents() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 KArgs kargs(su2_ensemble_s *E, int which = 0) {
     KArgs a;
     a.desc = E->ddesc;
@@ -604,18 +626,17 @@ su2_status set_links_l(su2_ensemble_s *E, int l, const double *host) {
     const long long V = 2LL * d.vh;
     for (long long i = 0; i < 4 * V; ++i)
         if (!finite_unit(host + 4 * i, 1e-6)) return SU2_EINVAL;
-    double *stage = nullptr;
-    CHK(dalloc(E, &stage, sizeof(double) * 16 * (size_t)E->total_sites));
+    TmpDev<double> stage;
+    CHK(dalloc(E, &stage.p, sizeof(double) * 16 * (size_t)E->total_sites));
     hipStream_t s = E->stream();
-    HIPCHK(hipMemcpyAsync(stage + 4 * d.off, host, sizeof(double) * 16 * V, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(stage.p + 4 * d.off, host, sizeof(double) * 16 * V, hipMemcpyHostToDevice, s));
     // only the tiles of lattice l
     KArgs a = kargs(E);
     a.tiles = E->tiles + d.tile0;
     a.ntiles = d.ntile;
-    su2::launch_from_canon(a, E->f32, stage, E->block, s);
+    su2::launch_from_canon(a, E->f32, stage.p, E->block, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipFree(stage));
     invalidate_measure_buffers(E);
     return SU2_OK;
 }
@@ -623,18 +644,17 @@ su2_status set_links_l(su2_ensemble_s *E, int l, const double *host) {
 su2_status get_links_l(su2_ensemble_s *E, int l, const void *src, int ndir, double *host) {
     const LatDesc &d = E->hdesc[l];
     const long long V = 2LL * d.vh;
-    double *stage = nullptr;
-    CHK(dalloc(E, &stage, sizeof(double) * 4 * ndir * (size_t)E->total_sites));
+    TmpDev<double> stage;
+    CHK(dalloc(E, &stage.p, sizeof(double) * 4 * ndir * (size_t)E->total_sites));
     hipStream_t s = E->stream();
     KArgs a = kargs(E);
     a.tiles = E->tiles + d.tile0;
     a.ntiles = d.ntile;
-    su2::launch_to_canon(a, E->f32, src, ndir, stage, E->block, s);
+    su2::launch_to_canon(a, E->f32, src, ndir, stage.p, E->block, s);
     HIPCHK(hipGetLastError());
     const long long base = ndir == 4 ? d.off : d.soff;
-    HIPCHK(hipMemcpyAsync(host, stage + 4 * base, sizeof(double) * 4 * ndir * V, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(host, stage.p + 4 * base, sizeof(double) * 4 * ndir * V, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipFree(stage));
     return SU2_OK;
 }
 
@@ -650,15 +670,14 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
     }
     if (updates) *updates = E->updates;
     if (defect) {
-        unsigned long long *m = nullptr;
-        CHK(dalloc(E, &m, sizeof(unsigned long long)));
-        HIPCHK(hipMemsetAsync(m, 0, sizeof(unsigned long long), E->stream()));
-        su2::launch_unit_defect(kargs(E), E->f32, m, E->block, E->stream());
+        TmpDev<unsigned long long> m;
+        CHK(dalloc(E, &m.p, sizeof(unsigned long long)));
+        HIPCHK(hipMemsetAsync(m.p, 0, sizeof(unsigned long long), E->stream()));
+        su2::launch_unit_defect(kargs(E), E->f32, m.p, E->block, E->stream());
         HIPCHK(hipGetLastError());
         unsigned long long bits = 0;
-        HIPCHK(hipMemcpyAsync(&bits, m, sizeof(bits), hipMemcpyDeviceToHost, E->stream()));
+        HIPCHK(hipMemcpyAsync(&bits, m.p, sizeof(bits), hipMemcpyDeviceToHost, E->stream()));
         HIPCHK(hipStreamSynchronize(E->stream()));
-        HIPCHK(hipFree(m));
         std::memcpy(defect, &bits, sizeof(double));
     }
     return check_err(E);
@@ -709,25 +728,30 @@ su2_status autotune_common(su2_ensemble_s *E) {
     if (tune_cache_get(key, cached)) return set_launch_common(E, cached.block, cached.grid, cached.remap, cached.nl);
 
     hipStream_t s = E->stream();
-    void *backup = nullptr;
-    CHK(dalloc(E, &backup, E->link_bytes));
-    HIPCHK(hipMemcpyAsync(backup, E->links, E->link_bytes, hipMemcpyDeviceToDevice, s));
+    TmpDev<char> backup;
+    CHK(dalloc(E, &backup.p, E->link_bytes));
+    HIPCHK(hipMemcpyAsync(backup.p, E->links, E->link_bytes, hipMemcpyDeviceToDevice, s));
     CHK(fold_tries(E));
     const unsigned long long tries0 = E->tries_acc, upd0 = E->updates;
     const DevState st0 = E->hst;
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, E->device));
     const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    const bool timing0 = E->timing;
+    struct TimingOff {  // timing is off while tuning and restored on every return path
+        su2_ensemble_s *E;
+        bool saved;
+        ~TimingOff() { E->timing = saved; }
+    } timing_off{E, E->timing};
     E->timing = false;
     CHK(ensure_series(E, 4));
 
     const int blocks[] = {64, 128, 256};
     const int gmul[] = {0, 4, 8, 16};
     const int nls[] = {1, 2, 4};
-    hipEvent_t ea, eb;
-    HIPCHK(hipEventCreate(&ea));
-    HIPCHK(hipEventCreate(&eb));
+    TmpEvents ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    hipEvent_t ea = ev.a, eb = ev.b;
     float best = 1e30f;
     Shape bestc{E->block, E->grid, E->remap, E->nl};
     for (int nl : nls)
@@ -752,18 +776,14 @@ su2_status autotune_common(su2_ensemble_s *E) {
                         bestc = Shape{b, g, rm, nl};
                     }
                 }
-    HIPCHK(hipEventDestroy(ea));
-    HIPCHK(hipEventDestroy(eb));
     CHK(set_launch_common(E, bestc.block, bestc.grid, bestc.remap, bestc.nl));
-    HIPCHK(hipMemcpyAsync(E->links, backup, E->link_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(E->links, backup.p, E->link_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(E->tries_part, 0, sizeof(unsigned long long) * E->ntiles, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipFree(backup));
     E->tries_acc = tries0;
     E->updates = upd0;
     E->hst = st0;
     CHK(upload_state(E));
-    E->timing = timing0;
     tune_cache_put(key, bestc);
     invalidate_measure_buffers(E);
     return SU2_OK;
@@ -1086,14 +1106,13 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     Timed t(E, SU2_K_WILSON, s);
     su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, E->wl_s, E->block, s);
     su2::launch_wtrace(va, E->f32, Rmax, Tmax, V, d.n[3], E->wl_s, E->wpart, E->block, s);
-    double *dout = nullptr;
-    CHK(dalloc(E, &dout, sizeof(double) * Rmax * Tmax));
-    su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout, s);
+    TmpDev<double> dout;
+    CHK(dalloc(E, &dout.p, sizeof(double) * Rmax * Tmax));
+    su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout.p, s);
     t.done(s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(out, dout, sizeof(double) * Rmax * Tmax, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(out, dout.p, sizeof(double) * Rmax * Tmax, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipFree(dout));
     return check_err(E);
 }
 
