@@ -35,12 +35,13 @@ HBM_PEAK_GBS = 8000.0
 # Bytes one heat-bath substep moves at 32^4 FP32, from rocprofv3 --pmc runs of
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the eight substeps
 # of a sweep), scaled by 2.0 and 1.0: the factors that make a 1 GiB device
-# copy read back its own size.  Valid only for the kernel sources with this
-# hash and the launch shape the counters were taken with (a grid of 0 counts
-# as its effective size, one workgroup per tile).
+# copy read back its own size.  Valid only for the sources with this hash
+# (kernels and the host code that orders their tiles) and the launch shape
+# the counters were taken with (a grid of 0 counts as its effective size,
+# one workgroup per tile).
 HB_TRAFFIC = {"sources_sha256": "b74b885270f16375681810a925a1bba174ecc297c9cee216773cdf026a5cb134",
               "launch": [128, 4096, 1, 1], "bytes": 80596199}
-KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp")
+KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp", "su2_api.hip")
 
 
 def kernel_sources_sha256():

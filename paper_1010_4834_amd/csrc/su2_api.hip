@@ -63,8 +63,9 @@ struct su2_ensemble_s {
     long long total_sites = 0;
 
     int block = 256, grid = 0, remap = 1, nl = 1;
-    std::vector<Tile> htiles, hstiles, hvtiles, hmtiles;
+    std::vector<Tile> htiles, hstiles, hvtiles, hmtiles, hmtiles_z;
     Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr, *mtiles = nullptr;
+    Tile *mtiles_z = nullptr;  // the heat-bath tiles of each lattice in (z, t, y, x) order
     int ntiles = 0, nstiles = 0, nvtiles = 0, nmtiles = 0;
 
     void *links = nullptr;
@@ -200,7 +201,8 @@ struct TmpEvents {
 KArgs kargs(su2_ensemble_s *E, int which = 0) {
     KArgs a;
     a.desc = E->ddesc;
-    a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : which == 2 ? E->vtiles : E->mtiles;
+    a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : which == 2 ? E->vtiles
+            : which == 3 ? E->mtiles : E->mtiles_z;
     a.ntiles = which == 0 ? E->ntiles : which == 1 ? E->nstiles : which == 2 ? E->nvtiles : E->nmtiles;
     a.xcd_remap = E->remap;
     a.links = E->links;
@@ -301,6 +303,7 @@ su2_status build_tiles(su2_ensemble_s *E) {
     E->hstiles.clear();
     E->hvtiles.clear();
     E->hmtiles.clear();
+    E->hmtiles_z.clear();
     const int B = E->block;
     for (int l = 0; l < E->n; ++l) {
         LatDesc &d = E->hdesc[l];
@@ -316,6 +319,18 @@ su2_status build_tiles(su2_ensemble_s *E) {
         d.mtile0 = (int)E->hmtiles.size();
         for (int s = 0; s < d.vh; s += B * E->nl) E->hmtiles.push_back(make_int2(l, s));
         d.nmtile = (int)E->hmtiles.size() - d.mtile0;
+        // The same tiles ordered by the (z, t, y, x) of their first site: the
+        // XCD-aware walk gives each XCD a contiguous share of the list, which
+        // in this order is a range of z over every t, so the temporal
+        // neighbours of the mu = 3 substeps stay in that XCD's L2.
+        std::vector<std::pair<long long, Tile>> zt;
+        for (int i = d.mtile0; i < d.mtile0 + d.nmtile; ++i) {
+            const long long cbs = E->hmtiles[i].y, row = cbs / d.hx;  // row = y + Ny (z + Nz t)
+            const long long y = row % d.n[1], z = (row / d.n[1]) % d.n[2], t = row / ((long long)d.n[1] * d.n[2]);
+            zt.push_back({((z * d.n[3] + t) * d.n[1] + y) * d.hx + cbs % d.hx, E->hmtiles[i]});
+        }
+        std::sort(zt.begin(), zt.end(), [](const auto &u, const auto &v) { return u.first < v.first; });
+        for (auto &e : zt) E->hmtiles_z.push_back(e.second);
     }
     E->ntiles = (int)E->htiles.size();
     E->nstiles = (int)E->hstiles.size();
@@ -325,6 +340,7 @@ su2_status build_tiles(su2_ensemble_s *E) {
     CHK(dalloc(E, &E->stiles, sizeof(Tile) * E->nstiles));
     CHK(dalloc(E, &E->vtiles, sizeof(Tile) * E->nvtiles));
     CHK(dalloc(E, &E->mtiles, sizeof(Tile) * E->nmtiles));
+    CHK(dalloc(E, &E->mtiles_z, sizeof(Tile) * E->nmtiles));
     CHK(dalloc(E, &E->tries_part, sizeof(unsigned long long) * E->ntiles));
     CHK(dalloc(E, &E->part_plaq, sizeof(double) * 4 * E->ntiles));
     {   // series partials of up to nslots sweeps (about 64 MiB at most),
@@ -351,6 +367,8 @@ su2_status build_tiles(su2_ensemble_s *E) {
     HIPCHK(hipMemcpyAsync(E->vtiles, E->hvtiles.data(), sizeof(Tile) * E->nvtiles, hipMemcpyHostToDevice,
                           E->stream()));
     HIPCHK(hipMemcpyAsync(E->mtiles, E->hmtiles.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    HIPCHK(hipMemcpyAsync(E->mtiles_z, E->hmtiles_z.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
                           E->stream()));
     CHK(upload_desc(E));
     HIPCHK(hipStreamSynchronize(E->stream()));
@@ -452,7 +470,7 @@ void destroy_common(su2_ensemble_s *E) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
-    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->st, E->tries_part, E->part_plaq,
+    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->mtiles_z, E->st, E->tries_part, E->part_plaq,
                     E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1],
                     E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
@@ -475,6 +493,7 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
+            a.tiles = mu == 3 ? E->mtiles_z : E->mtiles;
             Timed t(E, SU2_K_HEATBATH, s, true);
             su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq,
                                  t.ev());
@@ -1011,8 +1030,8 @@ su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int m
     hipStream_t s = E->stream();
     {
         Timed t(E, SU2_K_HEATBATH, s, true);
-        su2::launch_heatbath(kargs(E, 3), E->f32, mu, parity, E->nl, E->block, E->grid, s, E->trace != nullptr,
-                             false, t.ev());
+        su2::launch_heatbath(kargs(E, mu == 3 ? 4 : 3), E->f32, mu, parity, E->nl, E->block, E->grid, s,
+                             E->trace != nullptr, false, t.ev());
         t.done(s);
     }
     HIPCHK(hipGetLastError());
