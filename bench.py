@@ -35,12 +35,12 @@ HBM_PEAK_GBS = 8000.0
 # Bytes one heat-bath substep moves at 32^4 FP32, from rocprofv3 --pmc runs of
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the eight substeps
 # of a sweep), scaled by 2.0 and 1.0: the factors that make a 1 GiB device
-# copy read back its own size.  Valid only for the sources with this hash
-# (kernels and the host code that orders their tiles) and the launch shape
-# the counters were taken with (a grid of 0 counts as its effective size,
-# one workgroup per tile).
-HB_TRAFFIC = {"sources_sha256": "b74b885270f16375681810a925a1bba174ecc297c9cee216773cdf026a5cb134",
-              "launch": [128, 4096, 1, 1], "bytes": 80596199}
+# copy read back its own size; bytes per launch for each launch shape
+# measured (block, grid, XCD remap, links per lane; a grid of 0 counts as its
+# effective size, one workgroup per tile).  Valid only for the sources with
+# this hash (the kernels and the host code that orders their tiles).
+HB_TRAFFIC = {"sources_sha256": "46db66e6d6c6d254b421d0d5260902577198e02a39656a9adca83cf3a4a3e467",
+              "by_launch": {(64, 8192, 1, 1): 78049323, (128, 4096, 1, 1): 78216058}}
 KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp", "su2_api.hip")
 
 
@@ -375,9 +375,8 @@ def main():
     # grid 0 = one workgroup per tile: the tile count rounded up to a multiple of 8
     tiles = -(-(updates_per_step // 8) // (block * nl))
     eff_grid = grid if grid > 0 else max(8, -(-tiles // 8) * 8)
-    if (args.config == "c2" and HB_TRAFFIC["bytes"] and [block, eff_grid, remap, nl] == HB_TRAFFIC["launch"]
-            and kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]):
-        traffic = HB_TRAFFIC["bytes"]
+    if args.config == "c2" and kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]:
+        traffic = HB_TRAFFIC["by_launch"].get((block, eff_grid, remap, nl))
     link_b = 16
     hb_bytes = (updates_per_step // 8) * 8 * link_b   # per substep: V/2 updates x 128 B
     achieved = hb_bytes / (hb_avg_us * 1e-6) / 1e9
