@@ -188,10 +188,12 @@ su2_status su2_load(const char *path, su2_lattice *out);
 
 /* Launch shape: threads per workgroup (64, 128, 192 or 256), resident
  * workgroups of the persistent grid (0 = one workgroup per tile; else a
- * multiple of 8), whether tiles are laid out per XCD (1) or round-robin (0),
- * and heat-bath links per lane (1, 2 or 4: a lane draws its links in one
- * rejection loop).  Link updates do not depend on it; reductions only in
- * rounding.  EINVAL for other values. */
+ * multiple of 8), the tile mode (0: tiles round-robin over the XCDs; 1: each
+ * XCD takes a contiguous share of the tile list; 2: as 1, with the heat-bath
+ * tiles of every direction in (z, t, y, x) order, which modes 0 and 1 use for
+ * the temporal direction only), and heat-bath links per lane (1, 2 or 4: a
+ * lane draws its links in one rejection loop).  Link updates do not depend
+ * on it; reductions only in rounding.  EINVAL for other values. */
 su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap, int links_per_lane);
 su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap, int *links_per_lane);
 /* Time the candidate launch shapes on this lattice and keep the fastest

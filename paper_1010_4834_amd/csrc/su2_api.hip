@@ -204,7 +204,7 @@ KArgs kargs(su2_ensemble_s *E, int which = 0) {
     a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : which == 2 ? E->vtiles
             : which == 3 ? E->mtiles : E->mtiles_z;
     a.ntiles = which == 0 ? E->ntiles : which == 1 ? E->nstiles : which == 2 ? E->nvtiles : E->nmtiles;
-    a.xcd_remap = E->remap;
+    a.xcd_remap = E->remap != 0;
     a.links = E->links;
     a.st = E->st;
     a.err = &E->st->err;
@@ -493,7 +493,8 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
-            a.tiles = mu == 3 ? E->mtiles_z : E->mtiles;
+            // (z, t, y, x) tile order for mu = 3, and for every mu in tile mode 2
+            a.tiles = (mu == 3 || E->remap == 2) ? E->mtiles_z : E->mtiles;
             Timed t(E, SU2_K_HEATBATH, s, true);
             su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq,
                                  t.ev());
@@ -705,7 +706,7 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
 su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, int nl) {
     if (block < 64 || block > 256 || (block & 63)) return SU2_EINVAL;
     if (grid < 0 || (grid & 7)) return SU2_EINVAL;
-    if (remap != 0 && remap != 1) return SU2_EINVAL;
+    if (remap < 0 || remap > 2) return SU2_EINVAL;
     if (nl != 1 && nl != 2 && nl != 4) return SU2_EINVAL;
     const bool reshape = block != E->block || nl != E->nl;
     E->grid = grid;
@@ -776,7 +777,7 @@ su2_status autotune_common(su2_ensemble_s *E) {
     for (int nl : nls)
         for (int b : blocks)
             for (int gm : gmul)
-                for (int rm = 0; rm < 2; ++rm) {
+                for (int rm = 0; rm < 3; ++rm) {
                     const int g = gm ? gm * cus / 8 * 8 : 0;
                     CHK(set_launch_common(E, b, g, rm, nl));
                     // series slots 0..3 of this candidate's four sweeps
@@ -1030,7 +1031,7 @@ su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int m
     hipStream_t s = E->stream();
     {
         Timed t(E, SU2_K_HEATBATH, s, true);
-        su2::launch_heatbath(kargs(E, mu == 3 ? 4 : 3), E->f32, mu, parity, E->nl, E->block, E->grid, s,
+        su2::launch_heatbath(kargs(E, (mu == 3 || E->remap == 2) ? 4 : 3), E->f32, mu, parity, E->nl, E->block, E->grid, s,
                              E->trace != nullptr, false, t.ev());
         t.done(s);
     }
