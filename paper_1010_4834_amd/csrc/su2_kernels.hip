@@ -542,6 +542,9 @@ __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
             udiv(row, d.n[1], d.inv_ny, z, y);
             Q<T> P = qone<T>();
             const int p0 = (x + y + z) & 1;
+            // unrolled so that the loads of several t issue together ahead
+            // of the (ordered) product chain
+#pragma unroll 4
             for (int t = 0; t < d.n[3]; ++t) {
                 const uint32_t cb = (uint32_t)(xs + d.ns * t) >> 1;
                 P = qmul(P, lds_(B, 3, (p0 + t) & 1, cb));
