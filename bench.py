@@ -383,6 +383,21 @@ def main():
     hb_bytes = (updates_per_step // 8) * 8 * link_b   # per substep: V/2 updates x 128 B
     achieved = hb_bytes / (hb_avg_us * 1e-6) / 1e9
     tries, updates = su2.su2_ensemble_stats(ens)
+    fp32_err = None
+    if n == 1:
+        # binary32 error of the measurements: the final configuration (its
+        # binary32 link values) measured by a binary32 and a binary64 lattice
+        U = su2.su2_ensemble_get_links(ens, 0, V_tot)
+        meas = {}
+        for prec in (su2.F32, su2.F64):
+            lat = su2.su2_create(*dims[0], su2.COLD, seed, prec)
+            su2.su2_set_stream(lat, stream.cuda_stream)
+            su2.su2_set_links(lat, U)
+            meas[prec] = (su2.su2_plaquette(lat), su2.su2_polyakov(lat))
+            su2.su2_destroy(lat)
+        (p32, l32), (p64, l64) = meas[su2.F32], meas[su2.F64]
+        fp32_err = {"plaquette": max(abs(a - b) for a, b in zip(p32, p64)), "polyakov": abs(l32 - l64),
+                    "form": "binary32 kernels (binary64 sums) vs binary64 on the same configuration"}
     su2.su2_ensemble_destroy(ens)
 
     out = {
@@ -413,6 +428,7 @@ def main():
         "plaquette": "summed inside the odd heat-bath substeps (no separate pass)",
         "step_GBs": updates_per_step * 8 * link_b / (secs / args.steps) / 1e9,
         "tries_per_update": tries / max(updates, 1),
+        "fp32_error": fp32_err,
         "gpu_event_ms": gpu_ms,
     }
 
