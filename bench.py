@@ -320,8 +320,8 @@ def main():
                     help="block,grid,xcd_remap,links_per_lane (skips tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(sharding is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is designed, not built)"}))
         sys.exit(2)
 
     import numpy as np

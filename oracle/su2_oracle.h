@@ -15,7 +15,7 @@
  * mu = 0,1,2 are x,y,z; mu = 3 is the temporal direction (the paper's U_4).
  *
  * Parity unpinned: the Philox counter layout, the uniform conversion, the
- * hybrid sampler switch and the sweep order are conventions of this build
+ * hybrid sampler switch and the sweep order are conventions of this code
  * (the paper uses an LCG / CURAND and prints no sampler code); they are
  * pinned only by agreement of independent implementations and statistics.
  */
