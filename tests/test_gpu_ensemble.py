@@ -132,3 +132,27 @@ def test_multi_sweep_graphs_match_direct_launches(su2, prec):
         assert np.array_equal(x, y)
     for x, y in zip(a[4], b[4]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("launch", [None, (128, 0, 2, 1)])
+def test_ensemble_fp64_c3_shapes(su2, orc, launch):
+    """The C3 beta scan at full size (16 x 32^3 x 4, beta in [2.1, 2.5], hot
+    start seed 3), binary64, one sweep under the autotuned launch shape and
+    under tile mode 2: sampled lattices against the oracle link by link, and
+    their plaquette and Polyakov series."""
+    dims = [(32, 32, 32, 4)] * 16
+    betas = [2.1 + 0.4 * i / 15 for i in range(16)]
+    ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=3, prec=su2.F64)
+    if launch is None:
+        su2.su2_ensemble_autotune(ens.h)
+    else:
+        su2.su2_ensemble_set_launch(ens.h, *launch)
+    print("launch", su2.su2_ensemble_get_launch(ens.h))
+    P, L = ens.run(1, 3)
+    for i in (0, 7, 15):
+        U = orc.hot(dims[i], 3, lat_id=i)
+        orc.heatbath_sweep(dims[i], U, betas[i], 3, 0, lat_id=i)
+        assert np.abs(ens.get_links(i) - U).max() < 1e-12, i
+        assert abs(P[i, 0] - orc.plaquette(dims[i], U)[0]) < 1e-12, i
+        assert abs(L[i, 0] - orc.polyakov(dims[i], U)) < 1e-12, i
+    ens.close()

@@ -295,6 +295,10 @@ def test_errors(su2):
         lat.wilson_loops(5, 2)
     with pytest.raises(su2.SU2Error):
         su2.su2_set_launch(lat.h, 100, 0, 1)
+    for bad in ((128, 0, 3, 1), (128, 0, -1, 1), (128, 12, 1, 1), (128, 0, 1, 3)):
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_set_launch(lat.h, *bad)
+        assert e.value.status == su2.EINVAL, bad
     with pytest.raises(su2.SU2Error) as e:
         lat.get_smeared()
     assert e.value.status == su2.ESTATE
