@@ -18,8 +18,10 @@ def su2():
 
 
 def test_ensemble_fp64_parity(su2, orc):
-    dims = [(4, 4, 4, 4), (6, 6, 6, 4), (8, 8, 8, 6), (4, 4, 4, 8), (6, 4, 2, 10)]
-    betas = [2.2, 2.35, 2.5, 2.65, 2.8]
+    # the last lattice is the smallest allowed (every neighbour pair wraps
+    # onto one site) at beta = 0 (the alpha = 0 branch for every link)
+    dims = [(4, 4, 4, 4), (6, 6, 6, 4), (8, 8, 8, 6), (4, 4, 4, 8), (6, 4, 2, 10), (2, 2, 2, 2)]
+    betas = [2.2, 2.35, 2.5, 2.65, 2.8, 0.0]
     ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=5, prec=su2.F64)
     P, L = ens.run(3, 5)
     for i, (d, b) in enumerate(zip(dims, betas)):

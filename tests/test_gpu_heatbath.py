@@ -97,8 +97,13 @@ def test_substeps_fp64(su2, orc, dims):
 
 
 @pytest.mark.parametrize("dims,beta,seed", [((8, 8, 8, 8), 2.3, 1), ((6, 4, 10, 6), 2.6, 3),
-                                            ((4, 6, 2, 8), 0.4, 9)])
+                                            ((4, 6, 2, 8), 0.4, 9), ((4, 4, 6, 4), 0.0, 11),
+                                            ((4, 4, 4, 6), 12.0, 5)])
 def test_sweep_fp64(su2, orc, dims, beta, seed):
+    """One binary64 sweep from a random configuration: links within 1e-12 of
+    the oracle and identical per-link try counts and sampler branches; beta = 0
+    is the alpha = 0 branch (a0 uniform on [-1, 1]), beta = 12 the deep
+    Kennedy-Pendleton regime (a0 near 1)."""
     V = int(np.prod(dims))
     U = inputs.random_config(dims, 32)
     lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
