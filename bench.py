@@ -13,12 +13,14 @@ stream it runs on), the plain FP64 single-lattice form on the same GPU for
 comparison, and the serial FP64 oracle timed on the host cores on a bounded
 sample.
 
-  python bench.py [--steps K] [--warmup W] [--config c2|control64|c3|c4|c5]
+  python bench.py [--steps K] [--warmup W] [--config c1|c2|c2x2|c2x4|c3|c4|c5|control64]
 
 The other configurations are side measurements of the same library: control64
-(a lattice larger than the Infinity Cache), c3 and c5 (ensembles; c5 also
-times the plain FP64 single-lattice form looped over its 64 lattices) and c4
-(24^3x48: heat bath, APE smearing and Wilson loops per configuration).
+(a lattice larger than the Infinity Cache), c2x2 and c2x4 (independent replica
+chains of the 32^4 lattice batched in one launch), c3 and c5 (ensembles; c3
+and c5 also time the plain FP64 single-lattice form looped over their
+lattices), c1 (8^4, binary64, launch-bound) and c4 (24^3x48: heat bath, APE
+smearing and Wilson loops per configuration).
 """
 import argparse
 import json
@@ -66,6 +68,13 @@ def configs():
     return {
         "c2": dict(dims=[(32, 32, 32, 32)], betas=[2.6], seed=2, poly=False,
                    desc="32^4 SU(2) heat bath, beta=2.6, hot start, 1 sweep + plaquette per step"),
+        "c2x2": dict(dims=[(32, 32, 32, 32)] * 2, betas=[2.6] * 2, seed=2, poly=False,
+                     desc="2 independent replica chains of the 32^4 lattice (beta=2.6, hot start, "
+                          "own lattice ids in the Philox counter) in one launch, 1 sweep + "
+                          "plaquette per step"),
+        "c2x4": dict(dims=[(32, 32, 32, 32)] * 4, betas=[2.6] * 4, seed=2, poly=False,
+                     desc="4 independent replica chains of the 32^4 lattice (256 MiB of links, "
+                          "the Infinity Cache's size) in one launch, 1 sweep + plaquette per step"),
         "control64": dict(dims=[(64, 64, 64, 64)], betas=[2.6], seed=2, poly=False,
                           desc="64^4 SU(2) heat bath (1 GiB of links, beyond the 256 MB "
                                "Infinity Cache), beta=2.6, 1 sweep + plaquette per step"),
