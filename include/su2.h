@@ -166,6 +166,10 @@ su2_status su2_get_smeared(su2_lattice lat, double *host);
  * (mu, parity) block. */
 su2_status su2_device_links(su2_lattice lat, void **device_ptr, size_t *bytes);
 
+/* Extents Nx, Ny, Nz, Nt of the lattice into dims[0..3], from which a caller
+ * sizes the host arrays above (V = Nx Ny Nz Nt).  EINVAL if dims is NULL. */
+su2_status su2_get_dims(su2_lattice lat, int *dims);
+
 /* Sweep counter (the Philox sweep word of the next sweep). */
 su2_status su2_get_sweep(su2_lattice lat, uint32_t *sweep);
 su2_status su2_set_sweep(su2_lattice lat, uint32_t sweep);
@@ -233,6 +237,12 @@ su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
  * directly. */
 su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, uint64_t seed, double *plaq,
                             double *poly);
+/* Number of lattices, and the extents Nx, Ny, Nz, Nt of lattice i into
+ * dims[0..3]: the series of su2_ensemble_run hold count*nsweeps values and
+ * the link arrays of lattice i V_i*16.  EINVAL for a NULL pointer or i out
+ * of range. */
+su2_status su2_ensemble_count(su2_ensemble ens, int *n);
+su2_status su2_ensemble_get_dims(su2_ensemble ens, int i, int *dims);
 su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
 su2_status su2_ensemble_set_links(su2_ensemble ens, int i, const double *host);
 su2_status su2_ensemble_stats(su2_ensemble ens, uint64_t *tries, uint64_t *updates);

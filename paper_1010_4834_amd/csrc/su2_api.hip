@@ -927,6 +927,24 @@ su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, uint64_t seed, double *
     return SU2_OK;
 }
 
+static su2_status dims_of(const su2_ensemble_s *E, int i, int *dims) {
+    if (!dims || i < 0 || i >= E->n) return SU2_EINVAL;
+    for (int k = 0; k < 4; ++k) dims[k] = E->hdesc[i].n[k];
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_count(su2_ensemble E, int *n) {
+    CHK(enter(E));
+    if (!n) return SU2_EINVAL;
+    *n = E->n;
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_get_dims(su2_ensemble E, int i, int *dims) {
+    CHK(enter(E));
+    return dims_of(E, i, dims);
+}
+
 su2_status su2_ensemble_get_links(su2_ensemble E, int i, double *host) {
     CHK(enter(E));
     if (i < 0 || i >= E->n || !host) return SU2_EINVAL;
@@ -1153,6 +1171,11 @@ su2_status su2_device_links(su2_lattice E, void **ptr, size_t *bytes) {
     if (ptr) *ptr = E->links;
     if (bytes) *bytes = E->link_bytes;
     return SU2_OK;
+}
+
+su2_status su2_get_dims(su2_lattice E, int *dims) {
+    CHK(enter(E));
+    return dims_of(E, 0, dims);
 }
 
 su2_status su2_get_sweep(su2_lattice E, uint32_t *sweep) {

@@ -63,6 +63,7 @@ _SIGS = {
     "su2_set_links": (_I, [_P, _P]),
     "su2_get_smeared": (_I, [_P, _P]),
     "su2_device_links": (_I, [_P, _PP, _P]),
+    "su2_get_dims": (_I, [_P, _P]),
     "su2_get_sweep": (_I, [_P, _P]),
     "su2_set_sweep": (_I, [_P, _U32]),
     "su2_stats": (_I, [_P, _P, _P, _P]),
@@ -80,6 +81,8 @@ _SIGS = {
     "su2_ensemble_set_stream": (_I, [_P, _P]),
     "su2_ensemble_set_sampler": (_I, [_P, _I]),
     "su2_ensemble_run": (_I, [_P, _I, _U64, _P, _P]),
+    "su2_ensemble_count": (_I, [_P, _P]),
+    "su2_ensemble_get_dims": (_I, [_P, _I, _P]),
     "su2_ensemble_get_links": (_I, [_P, _I, _P]),
     "su2_ensemble_set_links": (_I, [_P, _I, _P]),
     "su2_ensemble_stats": (_I, [_P, _P, _P]),
@@ -106,10 +109,23 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def _f64(a, n):
+def _f64(a, n, where):
+    """A C-contiguous float64 copy or view of exactly n values: the library
+    reads n values from the pointer, so any other size is refused here."""
     a = np.ascontiguousarray(a, dtype=np.float64)
-    assert a.size == n, (a.size, n)
+    if a.size != n:
+        raise ValueError(f"{where}: {a.size} values given, the lattice needs {n}")
     return a
+
+
+def _sites(h, volume, where, i=None):
+    """Site count of the handle's lattice (lattice i of an ensemble), from the
+    library; a caller-supplied volume must agree with it."""
+    d = su2_get_dims(h) if i is None else su2_ensemble_get_dims(h, i)
+    V = d[0] * d[1] * d[2] * d[3]
+    if volume is not None and int(volume) != V:
+        raise ValueError(f"{where}: volume {volume} given, the lattice has {V} sites")
+    return V
 
 
 # ---- C names -----------------------------------------------------------------
@@ -170,19 +186,19 @@ def su2_wilson_loops(h, rmax, tmax):
     return out
 
 
-def su2_get_links(h, volume):
-    out = np.zeros((volume, 4, 4))
+def su2_get_links(h, volume=None):
+    out = np.zeros((_sites(h, volume, "su2_get_links"), 4, 4))
     _chk(_lib.su2_get_links(h, _ptr(out)), "su2_get_links")
     return out
 
 
 def su2_set_links(h, links):
-    a = _f64(links, links.size)
+    a = _f64(links, 16 * _sites(h, None, "su2_set_links"), "su2_set_links")
     _chk(_lib.su2_set_links(h, _ptr(a)), "su2_set_links")
 
 
-def su2_get_smeared(h, volume):
-    out = np.zeros((volume, 3, 4))
+def su2_get_smeared(h, volume=None):
+    out = np.zeros((_sites(h, volume, "su2_get_smeared"), 3, 4))
     _chk(_lib.su2_get_smeared(h, _ptr(out)), "su2_get_smeared")
     return out
 
@@ -191,6 +207,12 @@ def su2_device_links(h):
     p, n = C.c_void_p(), C.c_size_t()
     _chk(_lib.su2_device_links(h, C.byref(p), C.byref(n)), "su2_device_links")
     return p.value, n.value
+
+
+def su2_get_dims(h):
+    d = np.zeros(4, dtype=np.int32)
+    _chk(_lib.su2_get_dims(h, _ptr(d)), "su2_get_dims")
+    return tuple(int(x) for x in d)
 
 
 def su2_get_sweep(h):
@@ -213,8 +235,8 @@ def su2_trace_tries(h, enable):
     _chk(_lib.su2_trace_tries(h, int(enable)), "su2_trace_tries")
 
 
-def su2_get_tries(h, volume):
-    out = np.zeros(volume * 4, dtype=np.uint32)
+def su2_get_tries(h, volume=None):
+    out = np.zeros(_sites(h, volume, "su2_get_tries") * 4, dtype=np.uint32)
     _chk(_lib.su2_get_tries(h, _ptr(out)), "su2_get_tries")
     return out
 
@@ -256,7 +278,8 @@ def su2_get_timing(h, kind):
 def su2_ensemble_create(dims, betas, start, seed, prec, device_links=None, device_bytes=0):
     d = np.ascontiguousarray(dims, dtype=np.int32).reshape(-1, 4)
     b = np.ascontiguousarray(betas, dtype=np.float64)
-    assert b.size == d.shape[0]
+    if b.size != d.shape[0]:
+        raise ValueError(f"su2_ensemble_create: {d.shape[0]} lattices but {b.size} couplings")
     h = C.c_void_p()
     _chk(_lib.su2_ensemble_create(d.shape[0], _ptr(d), _ptr(b), start, seed, prec, device_links,
                                   device_bytes, C.byref(h)), "su2_ensemble_create")
@@ -275,7 +298,26 @@ def su2_ensemble_set_sampler(h, sampler):
     _chk(_lib.su2_ensemble_set_sampler(h, sampler), "su2_ensemble_set_sampler")
 
 
+def su2_ensemble_count(h):
+    n = C.c_int()
+    _chk(_lib.su2_ensemble_count(h, C.byref(n)), "su2_ensemble_count")
+    return n.value
+
+
+def su2_ensemble_get_dims(h, i):
+    d = np.zeros(4, dtype=np.int32)
+    _chk(_lib.su2_ensemble_get_dims(h, i, _ptr(d)), "su2_ensemble_get_dims")
+    return tuple(int(x) for x in d)
+
+
 def su2_ensemble_run(h, n, nsweeps, seed, plaq=True, poly=True):
+    # the library writes count * nsweeps values per series
+    if n is None:
+        n = su2_ensemble_count(h)
+    elif int(n) != su2_ensemble_count(h):
+        raise ValueError(f"su2_ensemble_run: n = {n} given, the ensemble has {su2_ensemble_count(h)} lattices")
+    if nsweeps < 0:
+        raise ValueError("su2_ensemble_run: nsweeps < 0")
     P = np.zeros((n, nsweeps)) if plaq else None
     L = np.zeros((n, nsweeps)) if poly else None
     _chk(_lib.su2_ensemble_run(h, nsweeps, seed, _ptr(P) if plaq else None,
@@ -283,14 +325,14 @@ def su2_ensemble_run(h, n, nsweeps, seed, plaq=True, poly=True):
     return P, L
 
 
-def su2_ensemble_get_links(h, i, volume):
-    out = np.zeros((volume, 4, 4))
+def su2_ensemble_get_links(h, i, volume=None):
+    out = np.zeros((_sites(h, volume, "su2_ensemble_get_links", i), 4, 4))
     _chk(_lib.su2_ensemble_get_links(h, i, _ptr(out)), "su2_ensemble_get_links")
     return out
 
 
 def su2_ensemble_set_links(h, i, links):
-    a = _f64(links, links.size)
+    a = _f64(links, 16 * _sites(h, None, "su2_ensemble_set_links", i), "su2_ensemble_set_links")
     _chk(_lib.su2_ensemble_set_links(h, i, _ptr(a)), "su2_ensemble_set_links")
 
 

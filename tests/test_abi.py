@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 import torch
 
@@ -64,3 +65,21 @@ def test_single_hip_runtime():
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def test_host_arrays_are_sized_by_the_binding():
+    """The library reads and writes whole lattices through bare pointers, so
+    the binding refuses a host array of any other size, and a null handle is
+    EINVAL for the extent queries (no GPU needed)."""
+    from paper_1010_4834_amd import su2
+    assert su2._f64(np.zeros((2, 4, 4)), 32, "t").dtype == np.float64
+    for bad in (np.zeros((2, 4, 4)), np.zeros(31)):
+        with pytest.raises(ValueError):
+            su2._f64(bad, 16 * 3, "t")
+    with pytest.raises(ValueError):
+        su2.su2_ensemble_create([(4, 4, 4, 4), (4, 4, 4, 6)], [2.0], su2.HOT, 1, su2.F32)
+    for call in (lambda: su2.su2_get_dims(None), lambda: su2.su2_ensemble_count(None),
+                 lambda: su2.su2_ensemble_get_dims(None, 0)):
+        with pytest.raises(su2.SU2Error) as e:
+            call()
+        assert e.value.status == su2.EINVAL

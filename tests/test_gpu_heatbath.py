@@ -310,3 +310,35 @@ def test_errors(su2):
     lat.heatbath(0.0, 2, 3)           # beta = 0: Haar draws, no hang
     assert lat.stats()[2] < 1e-6
     lat.close()
+
+
+def test_extents_and_host_sizes(su2):
+    """The extent queries return what the handles were created with, and the
+    binding refuses a host array or volume that disagrees with them (the
+    library itself reads and writes whole lattices through bare pointers)."""
+    lat = su2.Lattice((4, 6, 2, 8), start=su2.COLD, prec=su2.F32)
+    assert su2.su2_get_dims(lat.h) == (4, 6, 2, 8)
+    with pytest.raises(ValueError):
+        su2.su2_get_links(lat.h, 100)
+    with pytest.raises(ValueError):
+        lat.set_links(np.zeros((10, 4, 4)))
+    with pytest.raises(ValueError):
+        su2.su2_get_tries(lat.h, 5)
+    assert su2.su2_get_links(lat.h).shape == (384, 4, 4)
+    lat.close()
+    ens = su2.Ensemble([(4, 4, 4, 4), (6, 4, 2, 8)], [2.0, 2.5], prec=su2.F32)
+    assert su2.su2_ensemble_count(ens.h) == 2
+    assert su2.su2_ensemble_get_dims(ens.h, 1) == (6, 4, 2, 8)
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_ensemble_get_dims(ens.h, 2)
+    assert e.value.status == su2.EINVAL
+    with pytest.raises(ValueError):
+        su2.su2_ensemble_run(ens.h, 1, 2, 3)
+    with pytest.raises(ValueError):
+        su2.su2_ensemble_get_links(ens.h, 0, 384)
+    with pytest.raises(ValueError):
+        ens.set_links(1, np.zeros((256, 4, 4)))
+    P, L = su2.su2_ensemble_run(ens.h, None, 2, 3)
+    assert P.shape == (2, 2) and L.shape == (2, 2) and np.isfinite(P).all()
+    assert ens.get_links(1).shape == (384, 4, 4)
+    ens.close()
