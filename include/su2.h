@@ -188,6 +188,10 @@ su2_status su2_get_tries(su2_lattice lat, uint32_t *host);
  * and the links in canonical float64.  A resumed run is bitwise identical
  * to an uninterrupted one (the random stream is counter based). */
 su2_status su2_save(su2_lattice lat, const char *path);
+/* EIO for anything but such a file: wrong magic or version, invalid extents
+ * or precision, a payload other than exactly 16 V float64 (checked before
+ * it is read), or links that are not unit quaternions; ENOMEM if the host
+ * copy of the links cannot be allocated.  *out is NULL on failure. */
 su2_status su2_load(const char *path, su2_lattice *out);
 
 /* Launch shape: threads per workgroup (64, 128, 192 or 256), resident

@@ -17,8 +17,12 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
+
+#include <sys/types.h>
 
 using su2::DevState;
 using su2::KArgs;
@@ -148,6 +152,19 @@ bool dims_ok(const int *d) {
 // 1/d rounded up to the next binary64, the reciprocal the device division
 // helper needs to truncate to floor(n/d) without a correction step.
 double recip_up(int d) { return std::nextafter(1.0 / d, HUGE_VAL); }
+
+// Host buffers sized by the caller or by the lattice: an allocation failure
+// becomes ENOMEM instead of an exception crossing the C ABI.
+template <class T> su2_status host_buf(std::vector<T> &v, size_t n) {
+    try {
+        v.resize(n);
+    } catch (const std::bad_alloc &) {
+        return SU2_ENOMEM;
+    } catch (const std::length_error &) {
+        return SU2_ENOMEM;
+    }
+    return SU2_OK;
+}
 
 su2_status enter(su2_ensemble_s *E) {
     if (!E) return SU2_EINVAL;
@@ -911,7 +928,8 @@ su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, uint64_t seed, double *
     CHK(upload_state(E));
     CHK(run_sweeps(E, nsweeps, meas));
     if (meas) {
-        std::vector<double> h((size_t)E->ser_cap * E->n);
+        std::vector<double> h;
+        CHK(host_buf(h, (size_t)E->ser_cap * E->n));
         hipStream_t s = E->stream();
         for (int m = 0; m < 2; ++m) {
             double *dst = m == 0 ? plaq : poly;
@@ -1229,7 +1247,8 @@ su2_status su2_save(su2_lattice E, const char *path) {
     if (!path) return SU2_EINVAL;
     const LatDesc &d = E->hdesc[0];
     const long long V = 2LL * d.vh;
-    std::vector<double> h((size_t)16 * V);
+    std::vector<double> h;
+    CHK(host_buf(h, (size_t)16 * V));
     CHK(get_links_l(E, 0, E->links, 4, h.data()));
     FILE *f = std::fopen(path, "wb");
     if (!f) return SU2_EIO;
@@ -1261,8 +1280,22 @@ su2_status su2_load(const char *path, su2_lattice *out) {
         std::fclose(f);
         return SU2_EIO;
     }
+    // The payload must be exactly the 16 V float64 the header announces,
+    // checked before anything is allocated for it.
     const long long V = (long long)hdr[0] * hdr[1] * hdr[2] * hdr[3];
-    std::vector<double> h((size_t)16 * V);
+    const long long payload = 16 * V * (long long)sizeof(double);
+    const off_t here = ftello(f);
+    off_t end = -1;
+    if (here >= 0 && fseeko(f, 0, SEEK_END) == 0) end = ftello(f);
+    if (end < here || (long long)(end - here) != payload || fseeko(f, here, SEEK_SET) != 0) {
+        std::fclose(f);
+        return SU2_EIO;
+    }
+    std::vector<double> h;
+    if (host_buf(h, (size_t)16 * V) != SU2_OK) {
+        std::fclose(f);
+        return SU2_ENOMEM;
+    }
     ok = std::fread(h.data(), 8, h.size(), f) == h.size();
     std::fclose(f);
     if (!ok) return SU2_EIO;

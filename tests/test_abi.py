@@ -83,3 +83,46 @@ def test_host_arrays_are_sized_by_the_binding():
         with pytest.raises(su2.SU2Error) as e:
             call()
         assert e.value.status == su2.EINVAL
+
+
+def _checkpoint(path, dims, prec, payload, magic=b"SU2CKPT1", version=1):
+    import struct
+    with open(path, "wb") as f:
+        f.write(magic + struct.pack("<I5iIQ", version, *dims, prec, 0, 1) + payload)
+
+
+def test_load_refuses_malformed_checkpoints(tmp_path):
+    """su2_load checks the header and that the payload is exactly 16 V
+    float64 before it allocates or reads it; all of this runs before any GPU
+    call, so it is tested here."""
+    from paper_1010_4834_amd import su2
+    cold = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), 256 * 4).tobytes()   # 4^4 sites, 4 links each
+    cases = {
+        "missing": None,
+        "magic": (b"SU2CKPT0", 1, (4, 4, 4, 4), su2.F32, cold),
+        "version": (b"SU2CKPT1", 2, (4, 4, 4, 4), su2.F32, cold),
+        "odd extent": (b"SU2CKPT1", 1, (4, 4, 5, 4), su2.F32, cold),
+        "precision": (b"SU2CKPT1", 1, (4, 4, 4, 4), 7, cold),
+        "short payload": (b"SU2CKPT1", 1, (4, 4, 4, 4), su2.F32, cold[:-8]),
+        "trailing bytes": (b"SU2CKPT1", 1, (4, 4, 4, 4), su2.F32, cold + b"\0"),
+        # 2^30 sites announce a 128 GiB payload that the file does not hold
+        "huge header": (b"SU2CKPT1", 1, (1024, 1024, 512, 2), su2.F32, b""),
+    }
+    for name, c in cases.items():
+        p = tmp_path / name.replace(" ", "_")
+        if c is not None:
+            magic, version, dims, prec, payload = c
+            _checkpoint(p, dims, prec, payload, magic, version)
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_load(str(p))
+        assert e.value.status == su2.EIO, name
+    # the well-formed file passes every check; without a GPU the lattice
+    # cannot be created
+    p = tmp_path / "good"
+    _checkpoint(p, (4, 4, 4, 4), su2.F32, cold)
+    try:
+        h = su2.su2_load(str(p))
+    except su2.SU2Error as e:
+        assert e.status == su2.ENODEV and not torch.cuda.is_available()
+    else:
+        su2.su2_destroy(h)
