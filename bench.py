@@ -249,7 +249,8 @@ def bench_c4(su2, args, cfg, stream):
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     W = np.asarray(W).ravel()
-    assert np.isfinite(W).all() and W[0] > 0
+    if not (np.isfinite(W).all() and W[0] > 0):
+        raise RuntimeError("Wilson loops invalid")
     su2.su2_set_timing(lat.h, 1)
     for _ in range(nconf):
         one_config()
@@ -372,7 +373,8 @@ def main():
     gpu_ms = e0.elapsed_time(e1)
     secs = max(wall, gpu_ms * 1e-3)
     value = updates_per_step * args.steps / secs
-    assert np.isfinite(P).all() and (P > 0).all() and (P < 1).all(), "plaquette series invalid"
+    if not (np.isfinite(P).all() and (P > 0).all() and (P < 1).all()):
+        raise RuntimeError("plaquette series invalid")
 
     # ---- dominant kernel: every heat-bath launch bracketed by HIP events ----
     su2.su2_ensemble_set_timing(ens, 1)
