@@ -56,6 +56,25 @@ def test_ensemble_fp32_c5_shapes(su2, orc):
     ens.close()
 
 
+def test_ensemble_fp64_c5_shapes(su2, orc):
+    """The 64-lattice uneven ensemble in binary64 under the autotuned launch
+    shape, one sweep: lattices of every extent class (8^3x4 up to 24^4)
+    against the oracle link by link, with their plaquette and Polyakov
+    values."""
+    dims, betas = inputs.c5_shapes()
+    ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=5, prec=su2.F64)
+    su2.su2_ensemble_autotune(ens.h)
+    print("launch", su2.su2_ensemble_get_launch(ens.h))
+    P, L = ens.run(1, 5)
+    for i in (0, 9, 15, 18, 27, 36, 45, 54, 63):
+        U = orc.hot(dims[i], 5, lat_id=i)
+        orc.heatbath_sweep(dims[i], U, betas[i], 5, 0, lat_id=i)
+        assert np.abs(ens.get_links(i) - U).max() < 1e-12, i
+        assert abs(P[i, 0] - orc.plaquette(dims[i], U)[0]) < 1e-12, i
+        assert abs(L[i, 0] - orc.polyakov(dims[i], U)) < 1e-12, i
+    ens.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("F64", 1e-13), ("F32", 2e-7)])
 def test_fused_plaquette_matches_standalone(su2, prec, tol):
     """The plaquette series summed inside the odd heat-bath substeps equals
