@@ -177,3 +177,41 @@ def test_ensemble_fp64_c3_shapes(su2, orc, launch):
         assert abs(P[i, 0] - orc.plaquette(dims[i], U)[0]) < 1e-12, i
         assert abs(L[i, 0] - orc.polyakov(dims[i], U)) < 1e-12, i
     ens.close()
+
+
+def test_handles_run_concurrently(su2):
+    """Separate handles are independent: two ensembles driven from two host
+    threads, each on its own stream, autotuning and sweeping at the same
+    time, end with the links and series of the same runs made one after the
+    other."""
+    import threading
+    import torch
+    jobs = [([(8, 6, 4, 10), (6, 6, 6, 4)], [2.4, 2.7], 21), ([(4, 4, 4, 8)] * 3, [2.2, 2.5, 2.8], 22)]
+
+    def run(dims, betas, seed, stream, out):
+        ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=seed, prec=su2.F32,
+                           stream=None if stream is None else stream.cuda_stream)
+        su2.su2_ensemble_set_launch(ens.h, 128, 0, 1, 1)
+        P, L = ens.run(12, seed)
+        out.append((P, L, [ens.get_links(i) for i in range(len(dims))]))
+        ens.close()
+
+    seq = []
+    for dims, betas, seed in jobs:
+        out = []
+        run(dims, betas, seed, None, out)
+        seq.append(out[0])
+    streams = [torch.cuda.Stream() for _ in jobs]
+    outs = [[] for _ in jobs]
+    threads = [threading.Thread(target=run, args=(d, b, s, st, o))
+               for (d, b, s), st, o in zip(jobs, streams, outs)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert all(not t.is_alive() for t in threads) and all(len(o) == 1 for o in outs)
+    for (P, L, U), o in zip(seq, outs):
+        P2, L2, U2 = o[0]
+        assert np.array_equal(P, P2) and np.array_equal(L, L2)
+        for a, b in zip(U, U2):
+            assert np.array_equal(a, b)
