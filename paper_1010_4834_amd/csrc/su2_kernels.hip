@@ -723,32 +723,24 @@ __global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const doubl
 // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)] with a binary64 norm.
 // src_raw: read the lattice links (first step) or the smeared buffer.
 // Grid row blockIdx.y = parity; a lane updates the three spatial links of
-// its site, which share several of their staple loads.
-template <class T, int MU>
-__device__ __forceinline__ void ape_link(const LatDesc &d, const Blocks<T, 3> &Bs, const Blocks<T, 3> &Bd,
-                                         int cb, int par, T alpha) {
-    const Site S = site_of(d, cb, par);
-    const int op = par ^ 1;
-    const int s_mu = S.s + step_fwd(d, S, MU);
+// its site.
+
+// Smeared value of one link from its own link u and, for the two other
+// spatial directions nu in ascending order (k = 0, 1), the three links of
+// each of its two staples; the norm is the binary64 1/|w| (a smeared sum is
+// in general far from unit norm, so there is no near-group shortcut).
+template <class T>
+__device__ __forceinline__ Q<T> ape_update(const Q<T> &u, const Q<T> (&a1)[2], const Q<T> (&a2)[2],
+                                           const Q<T> (&a3)[2], const Q<T> (&b1)[2], const Q<T> (&b2)[2],
+                                           const Q<T> (&b3)[2], T alpha) {
     Q<T> sum{T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int nu = 0; nu < 3; ++nu) {
-        if (nu == MU) continue;
-        const int fn = step_fwd(d, S, nu), bn = step_bwd(d, S, nu);
-        const Q<T> a1 = lds_(Bs, nu, par, (uint32_t)S.s >> 1);
-        const Q<T> a2 = lds_(Bs, MU, op, (uint32_t)(S.s + fn) >> 1);
-        const Q<T> a3 = lds_(Bs, nu, op, (uint32_t)s_mu >> 1);
-        const Q<T> b1 = lds_(Bs, nu, op, (uint32_t)(S.s + bn) >> 1);
-        const Q<T> b2 = lds_(Bs, MU, op, (uint32_t)(S.s + bn) >> 1);
-        const Q<T> b3 = lds_(Bs, nu, par, (uint32_t)(s_mu + bn) >> 1);
-        qmul_acc(sum, qmul(a1, a2), qdag(a3));
-        qmul_acc(sum, qmul(qdag(b1), b2), b3);
+    for (int k = 0; k < 2; ++k) {
+        qmul_acc(sum, qmul(a1[k], a2[k]), qdag(a3[k]));
+        qmul_acc(sum, qmul(qdag(b1[k]), b2[k]), b3[k]);
     }
-    const Q<T> u = lds_(Bs, MU, par, (uint32_t)cb);
     const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
     const Q<T> w{w0 * u.a + w1 * sum.a, w0 * u.b + w1 * sum.b, w0 * u.c + w1 * sum.c, w0 * u.d + w1 * sum.d};
-    // projection onto SU(2): scale by the binary64 1/|w| (a smeared sum is
-    // in general far from unit norm, so no near-group shortcut)
     const double wa = w.a, wb = w.b, wc = w.c, wd = w.d;
     const double n2 = wa * wa + wb * wb + wc * wc + wd * wd;
     Q<T> un = u;
@@ -756,7 +748,56 @@ __device__ __forceinline__ void ape_link(const LatDesc &d, const Blocks<T, 3> &B
         const double f = 1.0 / sqrt(n2);
         un = Q<T>{(T)(wa * f), (T)(wb * f), (T)(wc * f), (T)(wd * f)};
     }
-    sts_(Bd, MU, par, (uint32_t)cb, un);
+    return un;
+}
+
+// APE step of the three spatial links of one site (paper Sec. 2, APE
+// equation).  Their twelve staples touch 24 distinct links: the three own
+// links O, the forward links F[m][n] = U_m(x+n), the backward links
+// K[n] = U_n(x-n) and M[m][n] = U_m(x-n), and the diagonal links
+// D[n][m] = U_n(x+m-n); each is loaded once.  O and D have the site's
+// parity, the others the opposite one.
+template <class T>
+__device__ __forceinline__ void ape_site(const LatDesc &d, const Blocks<T, 3> &Bs, const Blocks<T, 3> &Bd, int cb,
+                                         int par, T alpha) {
+    const Site S = site_of(d, cb, par);
+    const int op = par ^ 1;
+    int f[3], b[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        f[m] = step_fwd(d, S, m);
+        b[m] = step_bwd(d, S, m);
+    }
+    Q<T> O[3], K[3], F[3][3], M[3][3], D[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        O[m] = lds_(Bs, m, par, (uint32_t)cb);
+        K[m] = lds_(Bs, m, op, (uint32_t)(S.s + b[m]) >> 1);
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            if (n == m) continue;
+            F[m][n] = lds_(Bs, m, op, (uint32_t)(S.s + f[n]) >> 1);
+            M[m][n] = lds_(Bs, m, op, (uint32_t)(S.s + b[n]) >> 1);
+            D[m][n] = lds_(Bs, m, par, (uint32_t)(S.s + f[n] + b[m]) >> 1);
+        }
+    }
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+        Q<T> a1[2], a2[2], a3[2], b1[2], b2[2], b3[2];
+        int k = 0;
+#pragma unroll
+        for (int nu = 0; nu < 3; ++nu) {
+            if (nu == mu) continue;
+            a1[k] = O[nu];
+            a2[k] = F[mu][nu];
+            a3[k] = F[nu][mu];
+            b1[k] = K[nu];
+            b2[k] = M[mu][nu];
+            b3[k] = D[nu][mu];
+            ++k;
+        }
+        sts_(Bd, mu, par, (uint32_t)cb, ape_update<T>(O[mu], a1, a2, a3, b1, b2, b3, alpha));
+    }
 }
 
 template <class T>
@@ -769,9 +810,7 @@ __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_r
         const Blocks<T, 3> Bd = blocks<T, 3>(dst, d.soff, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        ape_link<T, 0>(d, Bs, Bd, cb, par, alpha);
-        ape_link<T, 1>(d, Bs, Bd, cb, par, alpha);
-        ape_link<T, 2>(d, Bs, Bd, cb, par, alpha);
+        ape_site<T>(d, Bs, Bd, cb, par, alpha);
     });
 }
 
