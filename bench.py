@@ -447,6 +447,9 @@ def main():
     if not args.no_fp64 and n == 1:
         lat = su2.su2_create(*dims[0], su2.HOT, seed, su2.F64)
         su2.su2_set_stream(lat, stream.cuda_stream)
+        if not args.no_tune:
+            su2.su2_autotune(lat, betas[0])
+        launch64 = su2.su2_get_launch(lat)
         su2.su2_heatbath(lat, betas[0], 5, seed)
         su2.su2_plaquette(lat)
         k64 = max(10, args.steps // 4)
@@ -466,6 +469,7 @@ def main():
         hb64_us = 1e3 * hb64_ms / hb64_n
         out["fp64_plain"] = {"value": v64, "ms_per_step": 1e3 * s64 / k64, "steps": k64,
                              "hb_avg_launch_us": hb64_us,
+                             "launch": dict(zip(("block", "grid", "xcd_remap", "links_per_lane"), launch64)),
                              "hb_GBs": (updates_per_step // 8) * 256 / (hb64_us * 1e-6) / 1e9,
                              "speedup_fp32_batched": value / v64}
 
