@@ -209,9 +209,10 @@ su2_status su2_get_launch(su2_lattice lat, int *block, int *grid, int *xcd_remap
 su2_status su2_autotune(su2_lattice lat, double beta);
 
 /* Per-kernel timing with HIP events on the handle's stream (enable = 1
- * also disables graph replay so every kernel is timed).  Heat-bath launches
- * have their events stamped by the launch itself with the kernel's start
- * and end; the other kernels are bracketed by event records.  get_timing
+ * also disables graph replay so every kernel is timed).  Heat-bath and
+ * over-relaxation launches have their events stamped by the launch itself
+ * with the kernel's start and end; the other kernels are bracketed by event
+ * records (which adds the dispatch latency).  get_timing
  * returns the summed milliseconds and launch count since enabling. */
 su2_status su2_set_timing(su2_lattice lat, int enable);
 su2_status su2_get_timing(su2_lattice lat, su2_kernel_kind kind, double *ms, int64_t *launches);

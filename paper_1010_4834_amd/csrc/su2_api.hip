@@ -1085,8 +1085,8 @@ su2_status su2_overrelax(su2_lattice E, int nsweeps) {
     for (int k = 0; k < nsweeps; ++k)
         for (int mu = 0; mu < 4; ++mu)
             for (int par = 0; par < 2; ++par) {
-                Timed t(E, SU2_K_OVERRELAX, s);
-                su2::launch_overrelax(a, E->f32, mu, par, E->block, E->grid, s);
+                Timed t(E, SU2_K_OVERRELAX, s, true);
+                su2::launch_overrelax(a, E->f32, mu, par, E->block, E->grid, s, t.ev());
                 t.done(s);
             }
     HIPCHK(hipGetLastError());

@@ -30,7 +30,8 @@ struct Ev {
 
 void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int block, int grid, hipStream_t s,
                      bool trace, bool plaq, const Ev &ev = Ev{});
-void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s);
+void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s,
+                      const Ev &ev = Ev{});
 void launch_init(const KArgs &a, bool f32, int hot, int block, int grid, hipStream_t s);
 void launch_from_canon(const KArgs &a, bool f32, const double *canon, int block, hipStream_t s);
 void launch_to_canon(const KArgs &a, bool f32, const void *src, int ndir, double *canon, int block,

@@ -1011,18 +1011,19 @@ void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int bloc
 }
 
 template <class T>
-static void launch_or_t(const KArgs &a, int mu, int par, int block, int grid, hipStream_t s) {
+static void launch_or_t(const KArgs &a, int mu, int par, int block, int grid, hipStream_t s, const Ev &ev) {
+    const dim3 g = grid_of(a, grid), b((unsigned)block);
     switch (mu) {
-    case 0: hipLaunchKernelGGL((k_overrelax<T, 0>), grid_of(a, grid), dim3(block), 0, s, a, par); break;
-    case 1: hipLaunchKernelGGL((k_overrelax<T, 1>), grid_of(a, grid), dim3(block), 0, s, a, par); break;
-    case 2: hipLaunchKernelGGL((k_overrelax<T, 2>), grid_of(a, grid), dim3(block), 0, s, a, par); break;
-    default: hipLaunchKernelGGL((k_overrelax<T, 3>), grid_of(a, grid), dim3(block), 0, s, a, par); break;
+    case 0: launch_ev(k_overrelax<T, 0>, g, b, s, ev, a, par); break;
+    case 1: launch_ev(k_overrelax<T, 1>, g, b, s, ev, a, par); break;
+    case 2: launch_ev(k_overrelax<T, 2>, g, b, s, ev, a, par); break;
+    default: launch_ev(k_overrelax<T, 3>, g, b, s, ev, a, par); break;
     }
 }
 
-void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s) {
-    if (f32) launch_or_t<float>(a, mu, par, block, grid, s);
-    else launch_or_t<double>(a, mu, par, block, grid, s);
+void launch_overrelax(const KArgs &a, bool f32, int mu, int par, int block, int grid, hipStream_t s, const Ev &ev) {
+    if (f32) launch_or_t<float>(a, mu, par, block, grid, s, ev);
+    else launch_or_t<double>(a, mu, par, block, grid, s, ev);
 }
 
 void launch_init(const KArgs &a, bool f32, int hot, int block, int grid, hipStream_t s) {
