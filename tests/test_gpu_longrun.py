@@ -57,12 +57,21 @@ def agree(name, a, b):
     assert z <= 3.0, name
 
 
-def test_plaquette_long_run(su2, orc):
-    dims, beta, n, discard, nbins = (10, 10, 10, 10), 2.3, 420, 60, 12
+P10 = dict(dims=(10, 10, 10, 10), beta=2.3, n=420, discard=60, nbins=12)
+
+
+@pytest.fixture(scope="module")
+def p10_ref(orc):
+    """<P> of a serial oracle heat-bath chain on 10^4 at beta = 2.3."""
     t0 = time.perf_counter()
-    Po, _ = oracle_series(orc, dims, beta, 101, n)
-    print(f"oracle {n} sweeps of {dims}: {time.perf_counter() - t0:.1f} s", flush=True)
-    ref = mean_err(Po, discard, nbins)
+    Po, _ = oracle_series(orc, P10["dims"], P10["beta"], 101, P10["n"])
+    print(f"oracle {P10['n']} sweeps of {P10['dims']}: {time.perf_counter() - t0:.1f} s", flush=True)
+    return mean_err(Po, P10["discard"], P10["nbins"])
+
+
+def test_plaquette_long_run(su2, p10_ref):
+    dims, beta, n, discard, nbins = P10["dims"], P10["beta"], P10["n"], P10["discard"], P10["nbins"]
+    ref = p10_ref
     for prec, seed in (("F32", 202), ("F64", 303)):
         Pg, _ = gpu_series(su2, dims, beta, seed, n, getattr(su2, prec))
         agree(f"<P> {prec} GPU vs oracle", mean_err(Pg, discard, nbins), ref)
@@ -71,6 +80,24 @@ def test_plaquette_long_run(su2, orc):
     Pb, _ = gpu_series(su2, dims, beta * 1.005, 404, n, su2.F32)
     m, e = mean_err(Pb, discard, nbins)
     assert abs(m - ref[0]) / np.hypot(e, ref[1]) > 3.0
+
+
+def test_overrelaxation_mix_long_run(su2, p10_ref):
+    """A chain of one heat-bath sweep and two over-relaxation sweeps per step
+    (binary32) reaches the equilibrium <P> of the oracle's pure heat-bath
+    chain: over-relaxation keeps the action and so the Boltzmann
+    distribution, and the mix is ergodic through the heat bath."""
+    dims, beta, n, discard, nbins = P10["dims"], P10["beta"], P10["n"], P10["discard"], P10["nbins"]
+    lat = su2.Lattice(dims, start=su2.HOT, seed=505, prec=su2.F32)
+    P = np.empty(n)
+    for k in range(n):
+        lat.heatbath(beta, 1, 505)
+        lat.overrelax(2)
+        P[k] = lat.plaquette()[0]
+    tries, updates, defect = lat.stats()
+    lat.close()
+    assert defect < 1e-5
+    agree("<P> F32 GPU 1 HB + 2 OR vs oracle HB", mean_err(P, discard, nbins), p10_ref)
 
 
 @pytest.mark.parametrize("beta", [2.2, 2.45])
