@@ -17,8 +17,9 @@
  *  - Host link arrays use the canonical layout: site s = x + Nx*(y + Ny*(z +
  *    Nz*t)), element [(s*4 + mu)*4 + c] with c = 0..3 the components
  *    (a0, a1, a2, a3) of U = a0 1 + i a.sigma (paper Sec. 2), in float64.
- *    Host pointers are borrowed for the duration of the call only; output
- *    arrays are sized by the caller.
+ *    Host pointers are borrowed for the duration of the call only; host
+ *    arrays are sized by the caller (su2_get_dims, su2_ensemble_count and
+ *    su2_ensemble_get_dims return the extents).
  *  - Device memory (the link buffer, smeared links, Wilson lines, reduction
  *    partials) is owned by the handle unless the caller passes its own link
  *    buffer to su2_create / su2_ensemble_create, which must then outlive the
