@@ -1095,10 +1095,12 @@ int wtrace_groups(const KArgs &a) {
     return g < 1024 ? (g < 8 ? 8 : g) : 1024;
 }
 
-// Column height of the Wilson trace: 4 when it divides Nt (binary32, up to
-// 16 time steps: more would spill registers), else 2 (extents are even).
+// Column height of the Wilson trace: in binary32 with up to 16 time steps,
+// 6 or else 4 when it divides Nt (the same four waves per SIMD; 8 would
+// spill registers); otherwise 2 (extents are even).
 template <class T> static int wtrace_nc(int Nt, int Tmax) {
-    return (sizeof(T) == 4 && Nt % 4 == 0 && Tmax <= 16) ? 4 : 2;
+    if (sizeof(T) == 4 && Tmax <= 16) return Nt % 6 == 0 ? 6 : Nt % 4 == 0 ? 4 : 2;
+    return 2;
 }
 
 template <class T, int NC>
@@ -1118,6 +1120,7 @@ static void launch_wtrace_t(const KArgs &a, int Rmax, int Tmax, long long V, int
                             int block, hipStream_t s) {
     const int nc = wtrace_nc<T>(Nt, Tmax);
     if constexpr (sizeof(T) == 4) {
+        if (nc == 6) return launch_wtrace_nc<T, 6>(a, Rmax, Tmax, V, sl, part, block, s);
         if (nc == 4) return launch_wtrace_nc<T, 4>(a, Rmax, Tmax, V, sl, part, block, s);
     }
     launch_wtrace_nc<T, 2>(a, Rmax, Tmax, V, sl, part, block, s);

@@ -84,11 +84,12 @@ def test_measurements_any_launch_shape(su2, orc, launch):
 @pytest.mark.parametrize("dims,Rm,Tm", [
     ((4, 2, 2, 20), 2, 18),   # more than 16 time steps (column height 2)
     ((2, 2, 4, 8), 2, 8),     # T = Nt: the temporal transport wraps the full period
-    ((2, 4, 2, 12), 2, 12),   # column height 4 in binary32 (Nt divisible by 4)
+    ((2, 4, 2, 12), 2, 12),   # column height 6 in binary32 (Nt divisible by 6)
+    ((2, 2, 2, 16), 2, 12),   # column height 4 in binary32 (Nt divisible by 4, not 6)
 ])
 def test_wilson_columns_and_long_times(su2, orc, dims, Rm, Tm):
     """The trace kernel takes columns of sites along t and transports the
-    temporal sides; long T, a full temporal wrap and both column heights
+    temporal sides; long T, a full temporal wrap and every column height
     against the oracle."""
     U = inputs.random_config(dims, 44)
     U32 = U.astype(np.float32).astype(np.float64)
