@@ -23,8 +23,15 @@
  *  - Device memory (the link buffer, smeared links, Wilson lines, reduction
  *    partials) is owned by the handle unless the caller passes its own link
  *    buffer to su2_create / su2_ensemble_create, which must then outlive the
- *    handle.  Calls are asynchronous on the handle's stream except those that
- *    return host results, which synchronise that stream.
+ *    handle.  Calls run on the handle's stream.  Calls that return host
+ *    results synchronise it, and so do the heat-bath and over-relaxation
+ *    sweep calls, which report their own numeric failures (below);
+ *    su2_heatbath_substep does not.
+ *  - SU2_ENUMERIC: a link whose staple is not finite (a non-finite
+ *    neighbour link) is not sampled; it becomes NaN and is counted, as is a
+ *    sampler that reaches its try cap.  The call that ran the update returns
+ *    SU2_ENUMERIC (a non-synchronising call: the next synchronising call),
+ *    and the count is cleared once reported.
  *  - A handle is not thread-safe; separate handles are independent.
  *  - Precision SU2_F32 keeps links in binary32 and does every global
  *    reduction and the reunitarisation norm in binary64 (compensated
@@ -85,7 +92,7 @@ typedef enum {
 const char *su2_status_str(su2_status st);
 
 /* Bytes of the native device link buffer of one lattice: 4*V links of 16 B
- * (F32) or 32 B (F64).  Returns 0 for invalid extents. */
+ * (F32) or 32 B (F64).  Returns 0 for invalid extents (see su2_create). */
 size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec);
 
 /* ---- one lattice ------------------------------------------------------ */
@@ -95,8 +102,9 @@ size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec);
  * Sec. 2).  The hot start draws Philox purpose 1 with `seed`.
  * device_links: optional caller-owned device buffer of su2_link_bytes()
  * bytes (NULL: the library allocates).  EINVAL on odd or < 2 extents, a
- * volume above 2^30 sites, Ny*Nz*Nt >= 2^24 or Nx >= 2^24, or a bad enum; ENODEV
- * without a GPU. */
+ * volume above 2^29 sites (SU2_F32) or 2^28 sites (SU2_F64) -- kernels address
+ * a link inside its (mu, parity) block with a 32-bit byte offset --,
+ * Ny*Nz*Nt >= 2^24 or Nx >= 2^24, or a bad enum; ENODEV without a GPU. */
 su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t seed,
                       su2_prec prec, void *device_links, size_t device_bytes,
                       su2_lattice *out);
@@ -112,18 +120,22 @@ su2_status su2_set_sampler(su2_lattice lat, su2_sampler sampler);
  * and a random direction; paper Sec. 4: chessboard order, separately by
  * direction and parity).  A sweep is mu = 0..3, even then odd.  The updated
  * link is renormalised with a binary64 norm.  beta >= 0 and finite,
- * nsweeps >= 0, else EINVAL.  ENUMERIC if a sampler hit its try cap
- * (non-finite links). */
+ * nsweeps >= 0, else EINVAL.  Synchronises; ENUMERIC if a staple was not
+ * finite or a sampler hit its try cap in these sweeps (the affected links
+ * are NaN). */
 su2_status su2_heatbath(su2_lattice lat, double beta, int nsweeps, uint64_t seed);
 
 /* A single (mu, parity) heat-bath substep with sweep index = the current
- * counter; the counter is not advanced (custom schedules, parity tests). */
+ * counter; the counter is not advanced (custom schedules, parity tests).
+ * Does not synchronise: a numeric failure is reported by the next
+ * synchronising call. */
 su2_status su2_heatbath_substep(su2_lattice lat, double beta, uint64_t seed, int mu,
                                 int parity);
 
 /* nsweeps over-relaxation sweeps (paper Sec. 2, over-relaxation equation):
  * U -> W^dag U^dag W^dag with W = V/sqrt(det V), which keeps Tr(U V); same
- * chessboard order; no random numbers; the sweep counter is not advanced. */
+ * chessboard order; no random numbers; the sweep counter is not advanced.
+ * Synchronises; ENUMERIC for a non-finite staple (that link becomes NaN). */
 su2_status su2_overrelax(su2_lattice lat, int nsweeps);
 
 /* Mean plaquette (paper Sec. 2, eq. for <P>): 1/2 Re Tr of the oriented
@@ -149,8 +161,8 @@ su2_status su2_ape_smear(su2_lattice lat, double alpha, int nsteps);
  * three spatial directions.  Spatial lines use the smeared links when
  * su2_ape_smear produced them since the last update, else the raw links;
  * the temporal sides always use the raw links.  The handle keeps a device
- * buffer of 3*Rmax*V spatial-line quaternions (grown on demand, freed with
- * the handle).  Rmax <= min(Nx,Ny,Nz), Tmax <= min(Nt, 32), else EINVAL.
+ * buffer of 3*Rmax*V spatial-line quaternions (grown on demand and kept, so
+ * that repeated measurements allocate nothing; freed with the handle).  Rmax <= min(Nx,Ny,Nz), Tmax <= min(Nt, 32), else EINVAL.
  * Synchronises. */
 su2_status su2_wilson_loops(su2_lattice lat, int Rmax, int Tmax, double *out);
 
@@ -185,14 +197,24 @@ su2_status su2_stats(su2_lattice lat, uint64_t *tries, uint64_t *updates,
 su2_status su2_trace_tries(su2_lattice lat, int enable);
 su2_status su2_get_tries(su2_lattice lat, uint32_t *host);
 
-/* Checkpoint: header (magic, version, extents, precision, sweep counter)
- * and the links in canonical float64.  A resumed run is bitwise identical
- * to an uninterrupted one (the random stream is counter based). */
+/* Configuration files (paper Sec. 4 kernel list: a configuration read from
+ * an input file as the third way to initialise the lattice).  All values
+ * little-endian.
+ * Checkpoint (su2_save): "SU2CKPT1", u32 version 1, i32 Nx Ny Nz Nt, i32
+ * precision, u32 sweep counter, u64 seed, then 16 V float64 links in the
+ * canonical layout.  A resumed run is bitwise identical to an uninterrupted
+ * one (the random stream is counter based).
+ * Configuration (su2_save_config): "SU2CONF1", i32 Nx Ny Nz Nt, then the
+ * 16 V float64 links in the canonical layout; no precision, seed or sweep
+ * counter, so any writer that knows the layout can produce one. */
 su2_status su2_save(su2_lattice lat, const char *path);
-/* EIO for anything but such a file: wrong magic or version, invalid extents
- * or precision, a payload other than exactly 16 V float64 (checked before
- * it is read), or links that are not unit quaternions; ENOMEM if the host
- * copy of the links cannot be allocated.  *out is NULL on failure. */
+su2_status su2_save_config(su2_lattice lat, const char *path);
+/* Reads either file.  A checkpoint restores precision, seed and sweep
+ * counter; a configuration gives a binary64 lattice with seed 0 and sweep
+ * counter 0.  EIO for anything else: wrong magic or version, invalid
+ * extents or precision, a payload other than exactly 16 V float64 (checked
+ * before it is read), or links that are not unit quaternions; ENOMEM if the
+ * host copy of the links cannot be allocated.  *out is NULL on failure. */
 su2_status su2_load(const char *path, su2_lattice *out);
 
 /* Launch shape: threads per workgroup (64, 128, 192 or 256), resident
@@ -231,18 +253,23 @@ su2_status su2_ensemble_destroy(su2_ensemble ens);
 su2_status su2_ensemble_set_stream(su2_ensemble ens, void *hip_stream);
 su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
 
-/* nsweeps heat-bath sweeps of every lattice at its own beta, with the mean
- * plaquette and Polyakov loop of every lattice after every sweep written to
- * plaq[i*nsweeps + k] and poly[i*nsweeps + k] (either may be NULL to skip
- * that measurement).  A sweep (eight substep launches; the plaquette is
- * summed inside the odd substeps) is captured in HIP graphs of one and of
- * several sweeps (8; environment SU2_GRAPH_SWEEPS) that are replayed;
- * per-sweep partial sums are reduced once per batch of up to 512 sweeps,
- * and the series stay on the device until the end.  Measuring does not
- * change the Markov chain.  Environment SU2_NO_GRAPH launches every kernel
- * directly. */
-su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, uint64_t seed, double *plaq,
-                            double *poly);
+/* nsweeps heat-bath sweeps of every lattice at its own beta (paper Sec. 2
+ * heat bath, Sec. 4 chessboard), with the mean plaquette and Polyakov loop
+ * (paper Sec. 2) of every lattice measured after every measure_every-th
+ * sweep: with M = nsweeps / measure_every, measurement k (after sweep
+ * (k+1)*measure_every of the run) of lattice i goes to plaq[i*M + k] and
+ * poly[i*M + k]; the last nsweeps % measure_every sweeps measure nothing.
+ * Either pointer may be NULL to skip that measurement.  The sweeps (eight
+ * substep launches each; the plaquette is summed inside the odd substeps of
+ * measured sweeps) are replayed from captured HIP graphs of up to 16 sweeps
+ * (environment SU2_GRAPH_SWEEPS) and of the smaller powers of two; partial
+ * sums are reduced once per batch of measurements and the series stay on
+ * the device until the end.  Measuring does not change the Markov chain.
+ * Synchronises once; ENUMERIC as for su2_heatbath.  measure_every >= 1,
+ * nsweeps >= 0, else EINVAL.  Environment SU2_NO_GRAPH launches every
+ * kernel directly. */
+su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, int measure_every, uint64_t seed,
+                            double *plaq, double *poly);
 /* Number of lattices, and the extents Nx, Ny, Nz, Nt of lattice i into
  * dims[0..3]: the series of su2_ensemble_run hold count*nsweeps values and
  * the link arrays of lattice i V_i*16.  EINVAL for a NULL pointer or i out
@@ -252,6 +279,10 @@ su2_status su2_ensemble_get_dims(su2_ensemble ens, int i, int *dims);
 su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
 su2_status su2_ensemble_set_links(su2_ensemble ens, int i, const double *host);
 su2_status su2_ensemble_stats(su2_ensemble ens, uint64_t *tries, uint64_t *updates);
+/* Per-link try record of later sweeps of every lattice (as su2_trace_tries);
+ * lattice i's record, V_i*4 uint32 in canonical [s][mu] order. */
+su2_status su2_ensemble_trace_tries(su2_ensemble ens, int enable);
+su2_status su2_ensemble_get_tries(su2_ensemble ens, int i, uint32_t *host);
 su2_status su2_ensemble_set_launch(su2_ensemble ens, int block, int grid, int xcd_remap,
                                    int links_per_lane);
 su2_status su2_ensemble_get_launch(su2_ensemble ens, int *block, int *grid, int *xcd_remap,

@@ -1,6 +1,6 @@
 """Build the serial FP64 oracle (test infrastructure) into oracle/liboracle.so.
 
-Plain gcc, -O2 -ffp-contract=off, no fast-math: the oracle's arithmetic is
+Plain gcc, -O3 -ffp-contract=off, no fast-math: the oracle's arithmetic is
 evaluated exactly as written.
 """
 import os
@@ -8,7 +8,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-FLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra"]
+FLAGS = ["-std=c11", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
 def build(verbose=False):

@@ -31,13 +31,12 @@ using su2::Tile;
 
 namespace {
 
-constexpr int NMEAS_GRAPHS = 4;  // measurement mask 0..3 (bit 0 plaquette, bit 1 Polyakov)
-// Sweeps per captured multi-sweep graph (SU2_GRAPH_SWEEPS overrides; 0 or 1
+// Sweeps per captured graph at most (SU2_GRAPH_SWEEPS overrides; 0 or 1
 // replays single-sweep graphs only).  Each graph launch leaves the GPU idle
-// for ~8 us before its first kernel (measured), so long runs replay a graph
-// of several sweeps and pay that once per graph.  Measured at 32^4: 8 sweeps
-// per graph beat 16, 32 and 64 (the per-launch cost grows with graph size).
-constexpr int GRAPH_SWEEPS_DEFAULT = 8;
+// for a few microseconds before its first kernel, so a run of n sweeps
+// replays as many graphs of this size as fit and then at most one graph of
+// each smaller power of two (20 sweeps: 16 + 4).
+constexpr int GRAPH_SWEEPS_DEFAULT = 16;
 int graph_sweeps() {
     static const int n = [] {
         const char *e = std::getenv("SU2_GRAPH_SWEEPS");
@@ -45,7 +44,13 @@ int graph_sweeps() {
     }();
     return n;
 }
-constexpr long long MAX_SITES = 1LL << 30;
+// Largest lattice per precision.  Kernels address a link inside its
+// (mu, parity) block with a 32-bit byte offset: cb * 16 in binary32 (below
+// 8 V bytes) and up to cb * 16 + 16 vh in binary64 (below 16 V bytes, the
+// (a2,a3) plane), so V <= 2^29 (binary32) and V <= 2^28 (binary64) keep every
+// offset below 2^32.
+constexpr long long MAX_SITES_F32 = 1LL << 29;
+constexpr long long MAX_SITES_F64 = 1LL << 28;
 
 struct EventPair {
     int kind;
@@ -92,9 +97,16 @@ struct su2_ensemble_s {
     double *ser_plaq = nullptr, *ser_poly = nullptr;
     int ser_cap = 0;
 
+    int ser_C = 1;                  // chunks per (lattice, sweep) of the series reduction
+    double *ser_chunk = nullptr;    // their (hi, lo) pairs
+    double *hser = nullptr;         // pinned host staging of the series
+    size_t hser_cap = 0;            // doubles
+    unsigned *herr = nullptr;       // pinned host copy of the error word
+
     hipStream_t own = nullptr, user = nullptr;
-    hipGraphExec_t gexec[NMEAS_GRAPHS] = {};   // one sweep
-    hipGraphExec_t gexecn[NMEAS_GRAPHS] = {};  // graph_sweeps() sweeps
+    // captured sweep graphs by (measurement mask, sweeps per measurement,
+    // measured units per graph)
+    std::map<unsigned long long, hipGraphExec_t> graphs;
 
     void *sm[2] = {nullptr, nullptr};
     int sm_cur = -1;  // index of the valid smeared buffer, -1 none
@@ -139,14 +151,14 @@ namespace {
 
 size_t link_size(bool f32) { return f32 ? 16 : 32; }
 
-bool dims_ok(const int *d) {
+bool dims_ok(const int *d, bool f32) {
     for (int k = 0; k < 4; ++k)
         if (d[k] < 2 || (d[k] & 1)) return false;
     long long V = (long long)d[0] * d[1] * d[2] * d[3];
     // site decompositions multiply quotients and divisors back with 24-bit
     // products; the largest quotient is Ny Nz Nt, the largest divisor Nx
     if ((long long)d[1] * d[2] * d[3] >= (1LL << 24) || d[0] >= (1 << 24)) return false;
-    return V <= MAX_SITES;
+    return V <= (f32 ? MAX_SITES_F32 : MAX_SITES_F64);
 }
 
 // 1/d rounded up to the next binary64, the reciprocal the device division
@@ -231,16 +243,14 @@ KArgs kargs(su2_ensemble_s *E, int which = 0) {
     a.sampler = E->sampler;
     a.advance = 0;
     a.nslots = 0;
+    a.every = 1;
     return a;
 }
 
 void drop_graphs(su2_ensemble_s *E) {
-    for (auto *set : {E->gexec, E->gexecn})
-        for (int i = 0; i < NMEAS_GRAPHS; ++i)
-            if (set[i]) {
-                (void)hipGraphExecDestroy(set[i]);
-                set[i] = nullptr;
-            }
+    for (auto &g : E->graphs)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
+    E->graphs.clear();
 }
 
 // ---- per-kernel event timing -------------------------------------------
@@ -367,6 +377,12 @@ su2_status build_tiles(su2_ensemble_s *E) {
     }
     CHK(dalloc(E, &E->part_poly, sizeof(double) * 2 * (size_t)E->nstiles * E->nslots));
     CHK(dalloc(E, &E->part_hb, sizeof(double) * 12 * (size_t)E->nmtiles * E->nslots));
+    {   // series reduction: chunks of ~256 partial tiles per (lattice, sweep)
+        int most = 1;
+        for (const LatDesc &d : E->hdesc) most = std::max(most, std::max(d.nmtile, d.nstile));
+        E->ser_C = std::min(64, std::max(1, (most + 255) / 256));
+        CHK(dalloc(E, &E->ser_chunk, sizeof(double) * 6 * (size_t)E->n * E->nslots * E->ser_C));
+    }
     {   // final-reduction workgroups per lattice: ~2048 partial tiles each
         int most = 1;
         for (const LatDesc &d : E->hdesc) most = std::max(most, std::max(d.nmtile, std::max(d.ntile, d.nstile)));
@@ -393,19 +409,28 @@ su2_status build_tiles(su2_ensemble_s *E) {
     return SU2_OK;
 }
 
-// upload seed / sweep / run_base (not the device-written error word)
+// Seed / sweep / run_base of the device state from the host mirror (not the
+// device-written error word), by a one-thread kernel in stream order: no
+// host synchronisation.
 su2_status upload_state(su2_ensemble_s *E) {
     E->hst.next = E->hst.sweep;
-    HIPCHK(hipMemcpyAsync(E->st, &E->hst, offsetof(DevState, err), hipMemcpyHostToDevice, E->stream()));
-    HIPCHK(hipStreamSynchronize(E->stream()));
+    su2::launch_set_state(E->st, E->hst.seed, E->hst.sweep, E->hst.run_base, E->stream());
+    HIPCHK(hipGetLastError());
     return SU2_OK;
 }
 
-su2_status check_err(su2_ensemble_s *E) {
-    unsigned int err = 0;
-    HIPCHK(hipMemcpyAsync(&err, &E->st->err, sizeof(err), hipMemcpyDeviceToHost, E->stream()));
+// End of a call that reports results: one synchronisation of the handle's
+// stream, after which the error word (non-finite staples, sampler try-cap
+// hits since the last report) is read.  A non-zero word is this call's
+// ENUMERIC and is cleared, so the next call starts clean.
+su2_status finish(su2_ensemble_s *E) {
+    HIPCHK(hipMemcpyAsync(E->herr, &E->st->err, sizeof(unsigned), hipMemcpyDeviceToHost, E->stream()));
     HIPCHK(hipStreamSynchronize(E->stream()));
-    return err ? SU2_ENUMERIC : SU2_OK;
+    if (*E->herr == 0u) return SU2_OK;
+    *E->herr = 0u;
+    su2::launch_clear_err(E->st, E->stream());
+    HIPCHK(hipGetLastError());
+    return SU2_ENUMERIC;
 }
 
 void invalidate_measure_buffers(su2_ensemble_s *E) { E->sm_cur = -1; }
@@ -463,6 +488,10 @@ su2_status create_common(int n, const int *dims, const double *betas, su2_start 
         E->hres = nullptr;
         return SU2_ENOMEM;
     }
+    if (hipHostMalloc((void **)&E->herr, sizeof(unsigned) * 16, hipHostMallocDefault) != hipSuccess) {
+        E->herr = nullptr;
+        return SU2_ENOMEM;
+    }
     E->hst.seed = seed;
     E->hst.sweep = 0;
     E->hst.run_base = 0;
@@ -488,25 +517,29 @@ void destroy_common(su2_ensemble_s *E) {
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
     void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->mtiles_z, E->st, E->tries_part, E->part_plaq,
-                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->sm[0], E->sm[1],
-                    E->wl_s, E->wpart, E->trace};
+                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->ser_chunk,
+                    E->sm[0], E->sm[1], E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (E->own_links && E->links) (void)hipFree(E->links);
     if (E->hres) (void)hipHostFree(E->hres);
+    if (E->hser) (void)hipHostFree(E->hser);
+    if (E->herr) (void)hipHostFree(E->herr);
     if (E->own) (void)hipStreamDestroy(E->own);
 }
 
 // ---- one sweep --------------------------------------------------------------
 // Eight substep launches that also advance the device sweep counter; with a
 // plaquette series the odd substeps mu >= 1 sum the plaquettes of the
-// sweep's final configuration into the sweep's partial slot, with a
-// Polyakov series k_polyakov does the same.  The slots are reduced per
-// batch of sweeps (series_batch), so a sweep holds no reduction launch.
-su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
+// sweep's final configuration into the partial slot of its measurement,
+// with a Polyakov series k_polyakov does the same.  The slots are reduced
+// per batch of measurements (series_batch), so a sweep holds no reduction
+// launch.
+su2_status enqueue_sweep(su2_ensemble_s *E, int meas, int every, hipStream_t s) {
     KArgs a = kargs(E, 3);
     a.advance = 1;
     a.nslots = E->nslots;
+    a.every = every;
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
@@ -520,6 +553,7 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
     if (meas & 2) {
         KArgs p = kargs(E, 1);
         p.nslots = E->nslots;
+        p.every = every;
         Timed t(E, SU2_K_POLYAKOV, s);
         su2::launch_polyakov(p, E->f32, E->part_poly, E->block, E->grid, s);
         t.done(s);
@@ -528,23 +562,29 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, hipStream_t s) {
     return SU2_OK;
 }
 
-// Series values of the nsw sweeps that started at host sweep index `first`.
-su2_status series_batch(su2_ensemble_s *E, int meas, unsigned first, int nsw, hipStream_t s) {
-    const unsigned k0 = first - E->hst.run_base;
+// One unit: `every` sweeps, the last of which measures (meas != 0).
+su2_status enqueue_unit(su2_ensemble_s *E, int meas, int every, hipStream_t s) {
+    for (int k = 0; k < every; ++k) CHK(enqueue_sweep(E, k == every - 1 ? meas : 0, every, s));
+    return SU2_OK;
+}
+
+// Series values of the nmeas measurements of units u0 .. u0 + nmeas - 1 of
+// the current run.
+su2_status series_batch(su2_ensemble_s *E, int meas, int u0, int nmeas, hipStream_t s) {
     Timed r(E, SU2_K_REDUCE, s);
     su2::launch_series(E->ddesc, E->n, (meas & 1) ? E->part_hb : nullptr, 12 * (long long)E->nmtiles,
-                       (meas & 2) ? E->part_poly : nullptr, 2 * (long long)E->nstiles, (int)(k0 % E->nslots),
-                       E->nslots, nsw, E->ser_plaq, E->ser_poly, E->ser_cap, (int)k0, s);
+                       (meas & 2) ? E->part_poly : nullptr, 2 * (long long)E->nstiles, u0 % E->nslots,
+                       E->nslots, nmeas, E->ser_C, E->ser_chunk, E->ser_plaq, E->ser_poly, E->ser_cap, u0, s);
     r.done(s);
     HIPCHK(hipGetLastError());
     return SU2_OK;
 }
 
-// Capture `count` consecutive sweeps into one executable graph.
-su2_status capture_sweeps(su2_ensemble_s *E, int meas, int count, hipGraphExec_t *out) {
+// Capture `units` consecutive units into one executable graph.
+su2_status capture_units(su2_ensemble_s *E, int meas, int every, int units, hipGraphExec_t *out) {
     HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
     su2_status st = SU2_OK;
-    for (int k = 0; k < count && st == SU2_OK; ++k) st = enqueue_sweep(E, meas, E->own);
+    for (int k = 0; k < units && st == SU2_OK; ++k) st = enqueue_unit(E, meas, every, E->own);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(E->own, &g);
     if (st != SU2_OK) {
@@ -558,40 +598,86 @@ su2_status capture_sweeps(su2_ensemble_s *E, int meas, int count, hipGraphExec_t
     return SU2_OK;
 }
 
-su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas) {
-    hipStream_t s = E->stream();
-    const bool use_graph = !E->timing && nsweeps > 1 && !std::getenv("SU2_NO_GRAPH");
-    // batches of at most nslots sweeps between series reductions
-    const int batch = meas ? E->nslots : nsweeps;
-    const int gs = graph_sweeps();
-    const bool multi = use_graph && gs > 1 && std::min(batch, nsweeps) >= gs;
-    if (use_graph && !E->gexec[meas]) CHK(capture_sweeps(E, meas, 1, &E->gexec[meas]));
-    if (multi && !E->gexecn[meas]) CHK(capture_sweeps(E, meas, gs, &E->gexecn[meas]));
-    for (int done = 0; done < nsweeps; done += batch) {
-        const int b = std::min(batch, nsweeps - done);
-        int k = 0;
-        if (multi)
-            for (; k + gs <= b; k += gs) HIPCHK(hipGraphLaunch(E->gexecn[meas], s));
-        for (; k < b; ++k) {
-            if (use_graph) HIPCHK(hipGraphLaunch(E->gexec[meas], s));
-            else CHK(enqueue_sweep(E, meas, s));
-        }
-        if (meas) CHK(series_batch(E, meas, E->hst.sweep + (unsigned)done, b, s));
+unsigned long long graph_key(int meas, int every, int units) {
+    return ((unsigned long long)(unsigned)units << 34) | ((unsigned long long)(unsigned)every << 2) |
+           (unsigned)meas;
+}
+
+// Units per graph: the largest graph holds G = max(1, graph_sweeps() / every)
+// units; the others 2^k < G units.  All of them are captured together on
+// the first run with this (meas, every), so later runs of any length only
+// replay graphs.
+int units_per_graph(int every) { return std::max(1, graph_sweeps() / every); }
+
+su2_status ensure_graphs(su2_ensemble_s *E, int meas, int every) {
+    const int G = units_per_graph(every);
+    std::vector<int> sizes{G};
+    for (int u = 1; u < G; u <<= 1) sizes.push_back(u);
+    for (int u : sizes) {
+        hipGraphExec_t &g = E->graphs[graph_key(meas, every, u)];
+        if (!g) CHK(capture_units(E, meas, every, u, &g));
     }
+    return SU2_OK;
+}
+
+// nunits units: graphs of G units, then the binary remainder (2^k < G).
+su2_status run_units(su2_ensemble_s *E, int nunits, int meas, int every) {
+    hipStream_t s = E->stream();
+    const bool use_graph = !E->timing && (long long)nunits * every > 1 && !std::getenv("SU2_NO_GRAPH");
+    if (!use_graph) {
+        for (int u = 0; u < nunits; ++u) CHK(enqueue_unit(E, meas, every, s));
+        return SU2_OK;
+    }
+    CHK(ensure_graphs(E, meas, every));
+    const int G = units_per_graph(every);
+    int left = nunits;
+    for (; left >= G; left -= G) HIPCHK(hipGraphLaunch(E->graphs[graph_key(meas, every, G)], s));
+    for (int u = 1 << 30; u >= 1; u >>= 1)
+        if (left & u) HIPCHK(hipGraphLaunch(E->graphs[graph_key(meas, every, u)], s));
+    return SU2_OK;
+}
+
+// nsweeps sweeps; with meas, sweep k (0-based) of the run is measured when
+// (k + 1) % every == 0 (nsweeps / every measurements, series batches of at
+// most nslots of them) and the remaining nsweeps % every sweeps at the end
+// measure nothing.
+su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every) {
+    const int nm = meas ? nsweeps / every : 0;
+    for (int done = 0; done < nm; done += E->nslots) {
+        const int b = std::min(E->nslots, nm - done);
+        CHK(run_units(E, b, meas, every));
+        CHK(series_batch(E, meas, done, b, E->stream()));
+    }
+    const int rest = nsweeps - nm * every;
+    if (rest > 0) CHK(run_units(E, rest, 0, 1));
     E->hst.sweep += (unsigned)nsweeps;
     E->updates += (unsigned long long)nsweeps * (unsigned long long)E->total_links;
     invalidate_measure_buffers(E);
     return SU2_OK;
 }
 
-su2_status ensure_series(su2_ensemble_s *E, int nsweeps) {
-    if (nsweeps <= E->ser_cap) return SU2_OK;
-    int cap = 64;
-    while (cap < nsweeps) cap *= 2;
-    CHK(dalloc(E, &E->ser_plaq, sizeof(double) * (size_t)cap * E->n));
-    CHK(dalloc(E, &E->ser_poly, sizeof(double) * (size_t)cap * E->n));
-    E->ser_cap = cap;
-    drop_graphs(E);
+// Device series of nm measurements per lattice and their pinned host
+// staging.
+su2_status ensure_series(su2_ensemble_s *E, int nm) {
+    if (nm > E->ser_cap) {
+        int cap = 64;
+        while (cap < nm) cap *= 2;
+        CHK(dalloc(E, &E->ser_plaq, sizeof(double) * (size_t)cap * E->n));
+        CHK(dalloc(E, &E->ser_poly, sizeof(double) * (size_t)cap * E->n));
+        E->ser_cap = cap;
+    }
+    const size_t need = 2 * (size_t)nm * E->n;
+    if (need > E->hser_cap) {
+        if (E->hser) (void)hipHostFree(E->hser);
+        E->hser = nullptr;
+        E->hser_cap = 0;
+        if (hipHostMalloc((void **)&E->hser, sizeof(double) * need, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            E->hser = nullptr;
+            return SU2_ENOMEM;
+        }
+        E->hser_cap = need;
+    }
     return SU2_OK;
 }
 
@@ -620,11 +706,12 @@ su2_status measure_plaquette(su2_ensemble_s *E, int l, double *avg, double *sp, 
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(E->hres, E->res, sizeof(double) * 4 * E->n, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    const su2_status st = finish(E);
+    if (st == SU2_EDEVICE) return st;
     if (avg) *avg = E->hres[4 * l + 0];
     if (sp) *sp = E->hres[4 * l + 1];
     if (tp) *tp = E->hres[4 * l + 2];
-    return check_err(E);
+    return st;
 }
 
 su2_status measure_polyakov(su2_ensemble_s *E, int l, double *out) {
@@ -643,9 +730,10 @@ su2_status measure_polyakov(su2_ensemble_s *E, int l, double *out) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(E->hres, E->res, sizeof(double) * 4 * E->n, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    const su2_status st = finish(E);
+    if (st == SU2_EDEVICE) return st;
     if (out) *out = E->hres[4 * l];
-    return check_err(E);
+    return st;
 }
 
 bool finite_unit(const double *u, double tol) {
@@ -663,10 +751,10 @@ su2_status set_links_l(su2_ensemble_s *E, int l, const double *host) {
     const long long V = 2LL * d.vh;
     for (long long i = 0; i < 4 * V; ++i)
         if (!finite_unit(host + 4 * i, 1e-6)) return SU2_EINVAL;
-    TmpDev<double> stage;
-    CHK(dalloc(E, &stage.p, sizeof(double) * 16 * (size_t)E->total_sites));
+    TmpDev<double> stage;   // lattice l only
+    CHK(dalloc(E, &stage.p, sizeof(double) * 16 * (size_t)V));
     hipStream_t s = E->stream();
-    HIPCHK(hipMemcpyAsync(stage.p + 4 * d.off, host, sizeof(double) * 16 * V, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(stage.p, host, sizeof(double) * 16 * V, hipMemcpyHostToDevice, s));
     // only the tiles of lattice l
     KArgs a = kargs(E);
     a.tiles = E->tiles + d.tile0;
@@ -681,16 +769,15 @@ su2_status set_links_l(su2_ensemble_s *E, int l, const double *host) {
 su2_status get_links_l(su2_ensemble_s *E, int l, const void *src, int ndir, double *host) {
     const LatDesc &d = E->hdesc[l];
     const long long V = 2LL * d.vh;
-    TmpDev<double> stage;
-    CHK(dalloc(E, &stage.p, sizeof(double) * 4 * ndir * (size_t)E->total_sites));
+    TmpDev<double> stage;   // lattice l only
+    CHK(dalloc(E, &stage.p, sizeof(double) * 4 * ndir * (size_t)V));
     hipStream_t s = E->stream();
     KArgs a = kargs(E);
     a.tiles = E->tiles + d.tile0;
     a.ntiles = d.ntile;
     su2::launch_to_canon(a, E->f32, src, ndir, stage.p, E->block, s);
     HIPCHK(hipGetLastError());
-    const long long base = ndir == 4 ? d.off : d.soff;
-    HIPCHK(hipMemcpyAsync(host, stage.p + 4 * base, sizeof(double) * 4 * ndir * V, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(host, stage.p, sizeof(double) * 4 * ndir * V, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return SU2_OK;
 }
@@ -717,7 +804,7 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
         HIPCHK(hipStreamSynchronize(E->stream()));
         std::memcpy(defect, &bits, sizeof(double));
     }
-    return check_err(E);
+    return finish(E);
 }
 
 su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, int nl) {
@@ -783,7 +870,9 @@ su2_status autotune_common(su2_ensemble_s *E) {
     CHK(ensure_series(E, 4));
 
     const int blocks[] = {64, 128, 256};
-    const int gmul[] = {0, 4, 8, 16};
+    // persistent grids of 4, 8, 16 workgroups per CU, and -1: as many as the
+    // heat-bath kernel keeps resident (its occupancy for the block size)
+    const int gmul[] = {0, 4, 8, 16, -1};
     const int nls[] = {1, 2, 4};
     TmpEvents ev;
     HIPCHK(hipEventCreate(&ev.a));
@@ -795,15 +884,17 @@ su2_status autotune_common(su2_ensemble_s *E) {
         for (int b : blocks)
             for (int gm : gmul)
                 for (int rm = 0; rm < 3; ++rm) {
-                    const int g = gm ? gm * cus / 8 * 8 : 0;
+                    const int per_cu = gm >= 0 ? gm : su2::heatbath_blocks_per_cu(E->f32, nl, b);
+                    const int g = per_cu > 0 ? per_cu * cus / 8 * 8 : 0;
+                    if (gm < 0 && per_cu <= 0) continue;
                     CHK(set_launch_common(E, b, g, rm, nl));
                     // series slots 0..3 of this candidate's four sweeps
                     E->hst = st0;
                     E->hst.run_base = st0.sweep;
                     CHK(upload_state(E));
-                    CHK(enqueue_sweep(E, 1, s));  // warm-up (with the plaquette series)
+                    CHK(enqueue_sweep(E, 1, 1, s));  // warm-up (with the plaquette series)
                     HIPCHK(hipEventRecord(ea, s));
-                    for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 1, s));
+                    for (int r = 0; r < 3; ++r) CHK(enqueue_sweep(E, 1, 1, s));
                     HIPCHK(hipEventRecord(eb, s));
                     HIPCHK(hipEventSynchronize(eb));
                     float ms = 0.f;
@@ -865,7 +956,7 @@ const char *su2_status_str(su2_status st) {
 
 size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec) {
     const int d[4] = {Nx, Ny, Nz, Nt};
-    if (!dims_ok(d) || (prec != SU2_F32 && prec != SU2_F64)) return 0;
+    if ((prec != SU2_F32 && prec != SU2_F64) || !dims_ok(d, prec == SU2_F32)) return 0;
     return (size_t)4 * Nx * Ny * Nz * (size_t)Nt * link_size(prec == SU2_F32);
 }
 
@@ -878,7 +969,7 @@ su2_status su2_ensemble_create(int n, const int *dims, const double *betas, su2_
     if (n > (1 << 23)) return SU2_EINVAL;
     long long sites = 0;
     for (int l = 0; l < n; ++l) {
-        if (!dims_ok(dims + 4 * l)) return SU2_EINVAL;
+        if (!dims_ok(dims + 4 * l, prec == SU2_F32)) return SU2_EINVAL;
         if (!(betas[l] >= 0.0) || !std::isfinite(betas[l])) return SU2_EINVAL;
         sites += (long long)dims[4 * l] * dims[4 * l + 1] * dims[4 * l + 2] * dims[4 * l + 3];
     }
@@ -917,32 +1008,33 @@ su2_status su2_ensemble_set_sampler(su2_ensemble E, su2_sampler sampler) {
     return SU2_OK;
 }
 
-su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, uint64_t seed, double *plaq, double *poly) {
+su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, int measure_every, uint64_t seed, double *plaq,
+                            double *poly) {
     CHK(enter(E));
-    if (nsweeps < 0) return SU2_EINVAL;
+    if (nsweeps < 0 || measure_every < 1) return SU2_EINVAL;
     if (nsweeps == 0) return SU2_OK;
     const int meas = (plaq ? 1 : 0) | (poly ? 2 : 0);
-    if (meas) CHK(ensure_series(E, nsweeps));
+    const int nm = meas ? nsweeps / measure_every : 0;
+    if (nm > 0) CHK(ensure_series(E, nm));
     E->hst.seed = seed;
     E->hst.run_base = E->hst.sweep;
     CHK(upload_state(E));
-    CHK(run_sweeps(E, nsweeps, meas));
-    if (meas) {
-        std::vector<double> h;
-        CHK(host_buf(h, (size_t)E->ser_cap * E->n));
-        hipStream_t s = E->stream();
-        for (int m = 0; m < 2; ++m) {
-            double *dst = m == 0 ? plaq : poly;
-            if (!dst) continue;
-            HIPCHK(hipMemcpyAsync(h.data(), m == 0 ? E->ser_plaq : E->ser_poly, sizeof(double) * h.size(),
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            for (int l = 0; l < E->n; ++l)
-                for (int k = 0; k < nsweeps; ++k) dst[(size_t)l * nsweeps + k] = h[(size_t)l * E->ser_cap + k];
-        }
-        return check_err(E);
+    CHK(run_sweeps(E, nsweeps, nm > 0 ? meas : 0, measure_every));
+    hipStream_t s = E->stream();
+    // both series into the pinned staging, then one synchronisation
+    for (int m = 0; m < 2 && nm > 0; ++m) {
+        if (!(m == 0 ? plaq : poly)) continue;
+        HIPCHK(hipMemcpy2DAsync(E->hser + (size_t)m * nm * E->n, sizeof(double) * nm,
+                                m == 0 ? E->ser_plaq : E->ser_poly, sizeof(double) * E->ser_cap,
+                                sizeof(double) * nm, E->n, hipMemcpyDeviceToHost, s));
     }
-    return SU2_OK;
+    const su2_status st = finish(E);
+    if (st == SU2_EDEVICE) return st;
+    for (int m = 0; m < 2 && nm > 0; ++m) {
+        double *dst = m == 0 ? plaq : poly;
+        if (dst) std::memcpy(dst, E->hser + (size_t)m * nm * E->n, sizeof(double) * nm * E->n);
+    }
+    return st;
 }
 
 static su2_status dims_of(const su2_ensemble_s *E, int i, int *dims) {
@@ -973,6 +1065,35 @@ su2_status su2_ensemble_set_links(su2_ensemble E, int i, const double *host) {
     CHK(enter(E));
     if (i < 0 || i >= E->n || !host) return SU2_EINVAL;
     return set_links_l(E, i, host);
+}
+
+static su2_status trace_common(su2_ensemble_s *E, int enable) {
+    CHK(enter(E));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    if (enable) {
+        if (!E->trace) {
+            CHK(dalloc(E, &E->trace, sizeof(uint32_t) * 4 * (size_t)E->total_sites));
+            HIPCHK(hipMemsetAsync(E->trace, 0, sizeof(uint32_t) * 4 * (size_t)E->total_sites, E->stream()));
+        }
+    } else if (E->trace) {
+        HIPCHK(hipFree(E->trace));
+        E->trace = nullptr;
+    }
+    drop_graphs(E);
+    return SU2_OK;
+}
+
+su2_status su2_ensemble_trace_tries(su2_ensemble E, int enable) { return trace_common(E, enable); }
+
+su2_status su2_ensemble_get_tries(su2_ensemble E, int i, uint32_t *host) {
+    CHK(enter(E));
+    if (i < 0 || i >= E->n || !host) return SU2_EINVAL;
+    if (!E->trace) return SU2_ESTATE;
+    const LatDesc &d = E->hdesc[i];
+    HIPCHK(hipMemcpyAsync(host, E->trace + d.toff, sizeof(uint32_t) * 8 * (size_t)d.vh, hipMemcpyDeviceToHost,
+                          E->stream()));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    return SU2_OK;
 }
 
 su2_status su2_ensemble_stats(su2_ensemble E, uint64_t *tries, uint64_t *updates) {
@@ -1015,8 +1136,8 @@ su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t 
     if (!out) return SU2_EINVAL;
     *out = nullptr;
     const int d[4] = {Nx, Ny, Nz, Nt};
-    if (!dims_ok(d)) return SU2_EINVAL;
     if ((start != SU2_COLD && start != SU2_HOT) || (prec != SU2_F32 && prec != SU2_F64)) return SU2_EINVAL;
+    if (!dims_ok(d, prec == SU2_F32)) return SU2_EINVAL;
     auto *E = new (std::nothrow) su2_lattice_s();
     if (!E) return SU2_ENOMEM;
     const double beta = 0.0;
@@ -1055,7 +1176,8 @@ su2_status su2_heatbath(su2_lattice E, double beta, int nsweeps, uint64_t seed) 
     if (nsweeps == 0) return SU2_OK;
     CHK(set_beta(E, beta));
     CHK(set_seed(E, seed));
-    return run_sweeps(E, nsweeps, 0);
+    CHK(run_sweeps(E, nsweeps, 0, 1));
+    return finish(E);
 }
 
 su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int mu, int parity) {
@@ -1090,8 +1212,9 @@ su2_status su2_overrelax(su2_lattice E, int nsweeps) {
                 t.done(s);
             }
     HIPCHK(hipGetLastError());
-    if (nsweeps) invalidate_measure_buffers(E);
-    return SU2_OK;
+    if (nsweeps == 0) return SU2_OK;
+    invalidate_measure_buffers(E);
+    return finish(E);
 }
 
 su2_status su2_plaquette(su2_lattice E, double *avg, double *sp, double *tp) {
@@ -1152,7 +1275,8 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     }
     const KArgs va = kargs(E, 2);
     const int nparts = su2::wtrace_groups(va);
-    const size_t pb = sizeof(double) * 2 * (size_t)Rmax * nparts * Tmax;
+    // partials, then the Rmax * Tmax results
+    const size_t pb = sizeof(double) * (2 * (size_t)Rmax * nparts * Tmax + (size_t)Rmax * Tmax);
     if (pb > E->wpart_bytes) {
         CHK(dalloc(E, &E->wpart, pb));
         E->wpart_bytes = pb;
@@ -1162,14 +1286,12 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     Timed t(E, SU2_K_WILSON, s);
     su2::launch_wlines(va, E->f32, sm ? E->sm[E->sm_cur] : E->links, sm ? 0 : 1, Rmax, E->wl_s, E->block, s);
     su2::launch_wtrace(va, E->f32, Rmax, Tmax, V, d.n[3], E->wl_s, E->wpart, E->block, s);
-    TmpDev<double> dout;
-    CHK(dalloc(E, &dout.p, sizeof(double) * Rmax * Tmax));
-    su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout.p, s);
+    double *dout = E->wpart + 2 * (size_t)Rmax * nparts * Tmax;
+    su2::launch_wfinal(E->ddesc, nparts, Rmax, Tmax, E->wpart, dout, s);
     t.done(s);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(out, dout.p, sizeof(double) * Rmax * Tmax, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return check_err(E);
+    HIPCHK(hipMemcpyAsync(out, dout, sizeof(double) * Rmax * Tmax, hipMemcpyDeviceToHost, s));
+    return finish(E);
 }
 
 su2_status su2_get_links(su2_lattice E, double *host) {
@@ -1214,21 +1336,7 @@ su2_status su2_stats(su2_lattice E, uint64_t *tries, uint64_t *updates, double *
     return stats_common(E, tries, updates, defect);
 }
 
-su2_status su2_trace_tries(su2_lattice E, int enable) {
-    CHK(enter(E));
-    HIPCHK(hipStreamSynchronize(E->stream()));
-    if (enable) {
-        if (!E->trace) {
-            CHK(dalloc(E, &E->trace, sizeof(uint32_t) * 4 * (size_t)E->total_sites));
-            HIPCHK(hipMemsetAsync(E->trace, 0, sizeof(uint32_t) * 4 * (size_t)E->total_sites, E->stream()));
-        }
-    } else if (E->trace) {
-        HIPCHK(hipFree(E->trace));
-        E->trace = nullptr;
-    }
-    drop_graphs(E);
-    return SU2_OK;
-}
+su2_status su2_trace_tries(su2_lattice E, int enable) { return trace_common(E, enable); }
 
 su2_status su2_get_tries(su2_lattice E, uint32_t *host) {
     CHK(enter(E));
@@ -1240,8 +1348,8 @@ su2_status su2_get_tries(su2_lattice E, uint32_t *host) {
     return SU2_OK;
 }
 
-// checkpoint format: "SU2CKPT1", u32 version, i32 Nx Ny Nz Nt, i32 prec,
-// u32 sweep, u64 seed, then 16 V float64 in the canonical layout
+// Checkpoint: "SU2CKPT1", u32 version, i32 Nx Ny Nz Nt, i32 prec, u32 sweep,
+// u64 seed, then 16 V float64 in the canonical layout (little-endian).
 su2_status su2_save(su2_lattice E, const char *path) {
     CHK(enter(E));
     if (!path) return SU2_EINVAL;
@@ -1264,6 +1372,41 @@ su2_status su2_save(su2_lattice E, const char *path) {
     return ok ? SU2_OK : SU2_EIO;
 }
 
+// Standalone configuration file: "SU2CONF1", i32 Nx Ny Nz Nt, then 16 V
+// float64 in the canonical layout (little-endian); no precision, seed or
+// sweep counter.
+su2_status su2_save_config(su2_lattice E, const char *path) {
+    CHK(enter(E));
+    if (!path) return SU2_EINVAL;
+    const LatDesc &d = E->hdesc[0];
+    const long long V = 2LL * d.vh;
+    std::vector<double> h;
+    CHK(host_buf(h, (size_t)16 * V));
+    CHK(get_links_l(E, 0, E->links, 4, h.data()));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return SU2_EIO;
+    const char magic[8] = {'S', 'U', '2', 'C', 'O', 'N', 'F', '1'};
+    const int32_t ext[4] = {d.n[0], d.n[1], d.n[2], d.n[3]};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(ext, 4, 4, f) == 4 &&
+              std::fwrite(h.data(), 8, h.size(), f) == h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? SU2_OK : SU2_EIO;
+}
+
+namespace {
+// The rest of the file must be exactly the 16 V float64 the header
+// announces, checked before anything is allocated for it; then read.
+su2_status read_payload(FILE *f, long long V, std::vector<double> &h) {
+    const long long payload = 16 * V * (long long)sizeof(double);
+    const off_t here = ftello(f);
+    off_t end = -1;
+    if (here >= 0 && fseeko(f, 0, SEEK_END) == 0) end = ftello(f);
+    if (end < here || (long long)(end - here) != payload || fseeko(f, here, SEEK_SET) != 0) return SU2_EIO;
+    CHK(host_buf(h, (size_t)16 * V));
+    return std::fread(h.data(), 8, h.size(), f) == h.size() ? SU2_OK : SU2_EIO;
+}
+}  // namespace
+
 su2_status su2_load(const char *path, su2_lattice *out) {
     if (!path || !out) return SU2_EINVAL;
     *out = nullptr;
@@ -1271,34 +1414,27 @@ su2_status su2_load(const char *path, su2_lattice *out) {
     if (!f) return SU2_EIO;
     char magic[8];
     uint32_t version = 0, sweep = 0;
-    int32_t hdr[5];
+    int32_t hdr[5] = {0, 0, 0, 0, (int32_t)SU2_F64};
     uint64_t seed = 0;
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "SU2CKPT1", 8) == 0 &&
-              std::fread(&version, 4, 1, f) == 1 && version == 1 && std::fread(hdr, 4, 5, f) == 5 &&
-              std::fread(&sweep, 4, 1, f) == 1 && std::fread(&seed, 8, 1, f) == 1;
-    if (!ok || !dims_ok(hdr) || (hdr[4] != SU2_F32 && hdr[4] != SU2_F64)) {
+    bool ok = std::fread(magic, 1, 8, f) == 8;
+    const bool ckpt = ok && std::memcmp(magic, "SU2CKPT1", 8) == 0;
+    const bool conf = ok && std::memcmp(magic, "SU2CONF1", 8) == 0;
+    if (ckpt)
+        ok = std::fread(&version, 4, 1, f) == 1 && version == 1 && std::fread(hdr, 4, 5, f) == 5 &&
+             std::fread(&sweep, 4, 1, f) == 1 && std::fread(&seed, 8, 1, f) == 1;
+    else if (conf)
+        ok = std::fread(hdr, 4, 4, f) == 4;   // binary64, seed 0, sweep 0
+    else
+        ok = false;
+    if (!ok || (hdr[4] != SU2_F32 && hdr[4] != SU2_F64) || !dims_ok(hdr, hdr[4] == SU2_F32)) {
         std::fclose(f);
         return SU2_EIO;
     }
-    // The payload must be exactly the 16 V float64 the header announces,
-    // checked before anything is allocated for it.
     const long long V = (long long)hdr[0] * hdr[1] * hdr[2] * hdr[3];
-    const long long payload = 16 * V * (long long)sizeof(double);
-    const off_t here = ftello(f);
-    off_t end = -1;
-    if (here >= 0 && fseeko(f, 0, SEEK_END) == 0) end = ftello(f);
-    if (end < here || (long long)(end - here) != payload || fseeko(f, here, SEEK_SET) != 0) {
-        std::fclose(f);
-        return SU2_EIO;
-    }
     std::vector<double> h;
-    if (host_buf(h, (size_t)16 * V) != SU2_OK) {
-        std::fclose(f);
-        return SU2_ENOMEM;
-    }
-    ok = std::fread(h.data(), 8, h.size(), f) == h.size();
+    const su2_status rs = read_payload(f, V, h);
     std::fclose(f);
-    if (!ok) return SU2_EIO;
+    if (rs != SU2_OK) return rs;
     su2_lattice E = nullptr;
     CHK(su2_create(hdr[0], hdr[1], hdr[2], hdr[3], SU2_COLD, seed, (su2_prec)hdr[4], nullptr, 0, &E));
     su2_status st = set_links_l(E, 0, h.data());
@@ -1307,6 +1443,7 @@ su2_status su2_load(const char *path, su2_lattice *out) {
         E->hst.seed = seed;
         st = upload_state(E);
     }
+    if (st == SU2_OK) st = finish(E);
     if (st != SU2_OK) {
         su2_destroy(E);
         return st == SU2_EINVAL ? SU2_EIO : st;

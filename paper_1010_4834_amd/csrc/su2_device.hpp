@@ -49,7 +49,7 @@ struct DevState {
     unsigned int sweep;     // Philox sweep word of the sweep in progress
     unsigned int next;      // sweep word of the following sweep
     unsigned int run_base;  // sweep index of the first sweep of a series
-    unsigned int err;       // sampler try-cap hits (non-finite input)
+    unsigned int err;       // non-finite staples and sampler try-cap hits
 };
 
 // A tile: lattice index and first index (half-site, spatial site or site).
@@ -223,6 +223,7 @@ template <> struct Mth<float> {
     static __device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
     static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
     static __device__ __forceinline__ float nan_() { return __builtin_nanf(""); }
+    static constexpr float MAXV = __FLT_MAX__;  // largest finite value
 };
 
 template <> struct Mth<double> {
@@ -243,6 +244,7 @@ template <> struct Mth<double> {
     static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     static __device__ __forceinline__ double nan_() { return __builtin_nan(""); }
+    static constexpr double MAXV = __DBL_MAX__;
 };
 
 // ---------------------------------------------------------------------------

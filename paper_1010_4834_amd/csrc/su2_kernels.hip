@@ -197,7 +197,8 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
     }
     double *plaq_part = a.plaq_part;
     if (PLAQ && a.nslots > 0)
-        plaq_part += (long long)((sweep - uni(a.st->run_base)) % (uint32_t)a.nslots) * 12 * a.ntiles;
+        plaq_part += (long long)(((sweep - uni(a.st->run_base)) / (uint32_t)a.every) % (uint32_t)a.nslots) * 12 *
+                     a.ntiles;
     TileWalk w(a.ntiles, a.xcd_remap);
     if (!w.ok()) return;
     int tile = w.tile();
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
         T alpha[NL], ial[NL];  // alpha = beta k and its reciprocal (0 when alpha = 0)
         Q<T> Wd[NL];
         Q<T> Vl[NL];  // summed staples of the planes nu < MU (PLAQ only)
-        uint32_t pend = 0;
+        uint32_t pend = 0, nonfinite = 0;
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
             const int cb = tl.y + m * (int)blockDim.x + (int)threadIdx.x;
@@ -221,11 +222,14 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
             ial[m] = T(0);
             Wd[m] = qone<T>();
             if (cb < d.vh) {
-                pend |= 1u << m;
                 Vl[m] = Q<T>{T(0), T(0), T(0), T(0)};
                 const Site S = site_of(d, cb, par);
                 const Q<T> V = staple<T, MU>(d, B, S, par, PLAQ ? &Vl[m] : nullptr);
                 const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
+                // a non-finite staple (a non-finite neighbour link) is not
+                // sampled: the link becomes NaN and the error word counts it
+                if (k2 <= M::MAXV) pend |= 1u << m;
+                else nonfinite |= 1u << m;
                 T k, ik;
                 if (sizeof(T) == 4) {
                     ik = M::rsqrt_(k2);
@@ -262,8 +266,11 @@ __global__ __launch_bounds__(256) void k_heatbath(KArgs a, int par) {
         uint32_t rec[NL];
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
-            delta[m] = T(0);
+            delta[m] = ((nonfinite >> m) & 1u) ? M::nan_() : T(0);
             rec[m] = 0;
+        }
+        if (__ballot(nonfinite != 0u)) {
+            if (nonfinite) atomicAdd(a.err, (unsigned)__popc(nonfinite));
         }
         // The loop runs while any lane of the wavefront has a link pending;
         // each pass is one try of every active lane, so the wavefront's try
@@ -358,6 +365,12 @@ __global__ __launch_bounds__(256) void k_overrelax(KArgs a, int par) {
         const Site S = site_of(d, cb, par);
         const Q<T> V = staple<T, MU>(d, B, S, par);
         const T k2 = V.a * V.a + V.b * V.b + V.c * V.c + V.d * V.d;
+        if (!(k2 <= Mth<T>::MAXV)) {  // non-finite staple: NaN link, counted
+            atomicAdd(a.err, 1u);
+            const T nan = Mth<T>::nan_();
+            sts_(B, MU, par, (uint32_t)cb, Q<T>{nan, nan, nan, nan});
+            return;
+        }
         if (!(k2 > T(0))) return;
         const T ik = T(1) / Mth<T>::sqrt_(k2);
         const Q<T> Wd{V.a * ik, -V.b * ik, -V.c * ik, -V.d * ik};
@@ -403,7 +416,8 @@ __global__ __launch_bounds__(256) void k_init(KArgs a, int hot) {
 }
 
 // Canonical float64 [s][mu][4] <-> native layout (ndir = 4: links,
-// ndir = 3: smeared spatial links).
+// ndir = 3: smeared spatial links).  One lattice per launch (the tile list
+// holds only its tiles); `canon` is that lattice's canonical array.
 template <class T>
 __global__ __launch_bounds__(256) void k_from_canon(KArgs a, const double *canon) {
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
@@ -412,7 +426,7 @@ __global__ __launch_bounds__(256) void k_from_canon(KArgs a, const double *canon
         const Blocks<T, 4> B = blocks<T, 4>(a.links, d.off, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        const double *c = canon + 4 * d.off;
+        const double *c = canon;
         for (int par = 0; par < 2; ++par) {
             const Site S = site_of(d, cb, par);
             for (int mu = 0; mu < 4; ++mu) {
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(256) void k_to_canon(KArgs a, const void *src, int 
         const Blocks<T, 4> B = blocks<T, 4>(src, base, d.vh);
         const int cb = tl.y + (int)threadIdx.x;
         if (cb >= d.vh) return;
-        double *c = canon + 4 * base;
+        double *c = canon;
         for (int par = 0; par < 2; ++par) {
             const Site S = site_of(d, cb, par);
             for (int mu = 0; mu < ndir; ++mu) {
@@ -529,7 +543,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_polyakov(KArgs a, double *part) {
     __shared__ DD lds[4];
     if (a.nslots > 0)
-        part += (long long)((uni(a.st->sweep) - uni(a.st->run_base)) % (uint32_t)a.nslots) * 2 * a.ntiles;
+        part += (long long)(((uni(a.st->sweep) - uni(a.st->run_base)) / (uint32_t)a.every) % (uint32_t)a.nslots) *
+                2 * a.ntiles;
     for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
         const Tile tl = load_tile(a.tiles, tile);
         const LatDesc d = load_desc(a.desc + tl.x);
@@ -654,16 +669,22 @@ __global__ __launch_bounds__(256) void k_finalize(const LatDesc *desc, const dou
     }
 }
 
-// Series values of a batch of sweeps: workgroup (l, j) sums lattice l's
-// partials of slot (slot0 + j) % nslots in a fixed order -- the heat-bath
-// plaquette partials [tile][plane slot 0, 1 spatial, 2 temporal][wavefront]
-// and the Polyakov (hi, lo) pairs -- and writes the mean plaquette and
-// Polyakov loop of sweep out0 + j.
-__global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const double *pp, long long pp_stride,
-                                                const double *pl, long long pl_stride, int slot0, int nslots,
-                                                double *outp, double *outl, long long ostride, int out0) {
+// Series values of a batch of measured sweeps, in two fixed-order passes.
+// k_series_part: workgroup (l C + c, j) sums chunk c of C of lattice l's
+// partials of slot (slot0 + j) % nslots -- the heat-bath plaquette partials
+// [tile][plane slot 0, 1 spatial, 2 temporal][wavefront] and the Polyakov
+// (hi, lo) pairs -- into three (hi, lo) pairs (spatial planes, temporal
+// planes, Polyakov).  k_series_final: workgroup (l, j) adds the C chunk pairs
+// in chunk order and writes the mean plaquette and Polyakov loop of sweep
+// out0 + j.  Many workgroups per sweep keep the partial reads (0.8 MB per
+// sweep at 32^4) off a single compute unit.
+__global__ __launch_bounds__(256) void k_series_part(const LatDesc *desc, const double *pp, long long pp_stride,
+                                                     const double *pl, long long pl_stride, int slot0, int nslots,
+                                                     int Cn, double *chunk) {
     __shared__ DD lds[3 * 4];
-    const int l = blockIdx.x, j = blockIdx.y;
+    // x: lattice-major (lattice, chunk) pairs (lattice counts beyond the
+    // y / z grid limits fit in x); y: measured sweep of the batch
+    const int C = Cn, c = blockIdx.x % Cn, l = blockIdx.x / Cn, j = blockIdx.y, nsw = gridDim.y;
     const long long slot = (slot0 + j) % nslots;
     const LatDesc d = load_desc(desc + l);
     DD a4[4][3];
@@ -672,16 +693,17 @@ __global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const doubl
 #pragma unroll
         for (int k = 0; k < 3; ++k) a4[u][k] = DD{0.0, 0.0};
     if (pp) {
+        int lo, hi;
+        chunk_range(d.nmtile, C, c, lo, hi);
         const double4 *q4 = reinterpret_cast<const double4 *>(pp + slot * pp_stride) + 3 * (long long)d.mtile0;
-        const int n = d.nmtile;
-        for (int t0 = (int)threadIdx.x; t0 < n; t0 += 4 * blockDim.x) {
+        for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
             double4 v[4][3];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int t = t0 + u * (int)blockDim.x;
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
-                    v[u][k] = t < n ? q4[3 * (long long)t + k] : make_double4(0.0, 0.0, 0.0, 0.0);
+                    v[u][k] = t < hi ? q4[3 * (long long)t + k] : make_double4(0.0, 0.0, 0.0, 0.0);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -694,13 +716,14 @@ __global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const doubl
         }
     }
     if (pl) {
+        int lo, hi;
+        chunk_range(d.nstile, C, c, lo, hi);
         const double2 *q2 = reinterpret_cast<const double2 *>(pl + slot * pl_stride) + d.stile0;
-        const int n = d.nstile;
-        for (int t0 = (int)threadIdx.x; t0 < n; t0 += 4 * blockDim.x) {
+        for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * blockDim.x) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int t = t0 + u * (int)blockDim.x;
-                if (t < n) a4[u][2] = dd_add(a4[u][2], DD{q2[t].x, q2[t].y});
+                if (t < hi) a4[u][2] = dd_add(a4[u][2], DD{q2[t].x, q2[t].y});
             }
         }
     }
@@ -709,11 +732,39 @@ __global__ __launch_bounds__(256) void k_series(const LatDesc *desc, const doubl
     for (int k = 0; k < 3; ++k) acc[k] = dd_add(dd_add(a4[0][k], a4[1][k]), dd_add(a4[2][k], a4[3][k]));
     dd_block_sum<3>(acc, lds);
     if (threadIdx.x == 0) {
-        const long long o = l * ostride + out0 + j;
-        if (pp) outp[o] = ((acc[0].hi + acc[0].lo) + (acc[1].hi + acc[1].lo)) / (12.0 * (double)d.vh);
-        if (pl) outl[o] = (acc[2].hi + acc[2].lo) / (double)d.ns;
+        double *o = chunk + 6 * (((long long)l * nsw + j) * C + c);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            o[2 * k] = acc[k].hi;
+            o[2 * k + 1] = acc[k].lo;
+        }
     }
 }
+
+__global__ __launch_bounds__(64) void k_series_final(const LatDesc *desc, const double *chunk, int C, bool plaq,
+                                                     bool poly, double *outp, double *outl, long long ostride,
+                                                     int out0) {
+    const int l = blockIdx.x, j = blockIdx.y, nsw = gridDim.y;
+    if (threadIdx.x != 0) return;
+    const double *ch = chunk + 6 * ((long long)l * nsw + j) * C;
+    DD tot[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int c = 0; c < C; ++c)
+        for (int k = 0; k < 3; ++k) tot[k] = dd_add(tot[k], DD{ch[6 * c + 2 * k], ch[6 * c + 2 * k + 1]});
+    const LatDesc d = load_desc(desc + l);
+    const long long o = l * ostride + out0 + j;
+    if (plaq) outp[o] = ((tot[0].hi + tot[0].lo) + (tot[1].hi + tot[1].lo)) / (12.0 * (double)d.vh);
+    if (poly) outl[o] = (tot[2].hi + tot[2].lo) / (double)d.ns;
+}
+
+// Device state words set from the host values without a host copy.
+__global__ void k_set_state(DevState *st, unsigned long long seed, unsigned sweep, unsigned run_base) {
+    st->seed = seed;
+    st->sweep = sweep;
+    st->next = sweep;
+    st->run_base = run_base;
+}
+
+__global__ void k_clear_err(DevState *st) { st->err = 0u; }
 
 // ---------------------------------------------------------------------------
 // APE smearing step (paper Sec. 2, APE equation) of the spatial links, all
@@ -1010,6 +1061,26 @@ void launch_heatbath(const KArgs &a, bool f32, int mu, int par, int nl, int bloc
     else launch_hb_t<double>(a, mu, par, nl, block, grid, s, trace, plaq, ev);
 }
 
+template <class T, int NL> static int hb_occ(int block) {
+    int best = 1 << 30;
+    const void *k[4] = {(const void *)k_heatbath<T, 0, false, NL, false>, (const void *)k_heatbath<T, 1, false, NL, false>,
+                        (const void *)k_heatbath<T, 2, false, NL, false>, (const void *)k_heatbath<T, 3, false, NL, false>};
+    for (const void *f : k) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        best = n < best ? n : best;
+    }
+    return best;
+}
+
+int heatbath_blocks_per_cu(bool f32, int nl, int block) {
+    if (f32) return nl == 1 ? hb_occ<float, 1>(block) : nl == 2 ? hb_occ<float, 2>(block) : hb_occ<float, 4>(block);
+    return nl == 1 ? hb_occ<double, 1>(block) : nl == 2 ? hb_occ<double, 2>(block) : hb_occ<double, 4>(block);
+}
+
 template <class T>
 static void launch_or_t(const KArgs &a, int mu, int par, int block, int grid, hipStream_t s, const Ev &ev) {
     const dim3 g = grid_of(a, grid), b((unsigned)block);
@@ -1064,11 +1135,19 @@ void launch_finalize(const LatDesc *desc, int nlat, int chunks, const double *pp
 }
 
 void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp_stride, const double *pl,
-                   long long pl_stride, int slot0, int nslots, int nsw, double *outp, double *outl,
-                   long long ostride, int out0, hipStream_t s) {
-    hipLaunchKernelGGL(k_series, dim3((unsigned)nlat, (unsigned)nsw), dim3(256), 0, s, desc, pp, pp_stride, pl,
-                       pl_stride, slot0, nslots, outp, outl, ostride, out0);
+                   long long pl_stride, int slot0, int nslots, int nsw, int C, double *chunk, double *outp,
+                   double *outl, long long ostride, int out0, hipStream_t s) {
+    hipLaunchKernelGGL(k_series_part, dim3((unsigned)(C * nlat), (unsigned)nsw), dim3(256), 0, s, desc, pp,
+                       pp_stride, pl, pl_stride, slot0, nslots, C, chunk);
+    hipLaunchKernelGGL(k_series_final, dim3((unsigned)nlat, (unsigned)nsw), dim3(64), 0, s, desc, chunk, C,
+                       pp != nullptr, pl != nullptr, outp, outl, ostride, out0);
 }
+
+void launch_set_state(DevState *st, unsigned long long seed, unsigned sweep, unsigned run_base, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st, seed, sweep, run_base);
+}
+
+void launch_clear_err(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(1), 0, s, st); }
 
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,

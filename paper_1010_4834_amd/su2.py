@@ -70,6 +70,7 @@ _SIGS = {
     "su2_trace_tries": (_I, [_P, _I]),
     "su2_get_tries": (_I, [_P, _P]),
     "su2_save": (_I, [_P, C.c_char_p]),
+    "su2_save_config": (_I, [_P, C.c_char_p]),
     "su2_load": (_I, [C.c_char_p, _PP]),
     "su2_set_launch": (_I, [_P, _I, _I, _I, _I]),
     "su2_get_launch": (_I, [_P, _P, _P, _P, _P]),
@@ -80,12 +81,14 @@ _SIGS = {
     "su2_ensemble_destroy": (_I, [_P]),
     "su2_ensemble_set_stream": (_I, [_P, _P]),
     "su2_ensemble_set_sampler": (_I, [_P, _I]),
-    "su2_ensemble_run": (_I, [_P, _I, _U64, _P, _P]),
+    "su2_ensemble_run": (_I, [_P, _I, _I, _U64, _P, _P]),
     "su2_ensemble_count": (_I, [_P, _P]),
     "su2_ensemble_get_dims": (_I, [_P, _I, _P]),
     "su2_ensemble_get_links": (_I, [_P, _I, _P]),
     "su2_ensemble_set_links": (_I, [_P, _I, _P]),
     "su2_ensemble_stats": (_I, [_P, _P, _P]),
+    "su2_ensemble_trace_tries": (_I, [_P, _I]),
+    "su2_ensemble_get_tries": (_I, [_P, _I, _P]),
     "su2_ensemble_set_launch": (_I, [_P, _I, _I, _I, _I]),
     "su2_ensemble_get_launch": (_I, [_P, _P, _P, _P, _P]),
     "su2_ensemble_autotune": (_I, [_P]),
@@ -245,6 +248,10 @@ def su2_save(h, path):
     _chk(_lib.su2_save(h, os.fsencode(path)), "su2_save")
 
 
+def su2_save_config(h, path):
+    _chk(_lib.su2_save_config(h, os.fsencode(path)), "su2_save_config")
+
+
 def su2_load(path):
     h = C.c_void_p()
     _chk(_lib.su2_load(os.fsencode(path), C.byref(h)), "su2_load")
@@ -310,17 +317,18 @@ def su2_ensemble_get_dims(h, i):
     return tuple(int(x) for x in d)
 
 
-def su2_ensemble_run(h, n, nsweeps, seed, plaq=True, poly=True):
-    # the library writes count * nsweeps values per series
+def su2_ensemble_run(h, n, nsweeps, seed, plaq=True, poly=True, measure_every=1):
+    # the library writes count * (nsweeps // measure_every) values per series
     if n is None:
         n = su2_ensemble_count(h)
     elif int(n) != su2_ensemble_count(h):
         raise ValueError(f"su2_ensemble_run: n = {n} given, the ensemble has {su2_ensemble_count(h)} lattices")
-    if nsweeps < 0:
-        raise ValueError("su2_ensemble_run: nsweeps < 0")
-    P = np.zeros((n, nsweeps)) if plaq else None
-    L = np.zeros((n, nsweeps)) if poly else None
-    _chk(_lib.su2_ensemble_run(h, nsweeps, seed, _ptr(P) if plaq else None,
+    if nsweeps < 0 or measure_every < 1:
+        raise ValueError("su2_ensemble_run: nsweeps < 0 or measure_every < 1")
+    m = nsweeps // measure_every
+    P = np.zeros((n, m)) if plaq else None
+    L = np.zeros((n, m)) if poly else None
+    _chk(_lib.su2_ensemble_run(h, nsweeps, measure_every, seed, _ptr(P) if plaq else None,
                                _ptr(L) if poly else None), "su2_ensemble_run")
     return P, L
 
@@ -340,6 +348,16 @@ def su2_ensemble_stats(h):
     t, u = C.c_uint64(), C.c_uint64()
     _chk(_lib.su2_ensemble_stats(h, C.byref(t), C.byref(u)), "su2_ensemble_stats")
     return t.value, u.value
+
+
+def su2_ensemble_trace_tries(h, enable):
+    _chk(_lib.su2_ensemble_trace_tries(h, int(enable)), "su2_ensemble_trace_tries")
+
+
+def su2_ensemble_get_tries(h, i, volume=None):
+    out = np.zeros(_sites(h, volume, "su2_ensemble_get_tries", i) * 4, dtype=np.uint32)
+    _chk(_lib.su2_ensemble_get_tries(h, i, _ptr(out)), "su2_ensemble_get_tries")
+    return out
 
 
 def su2_ensemble_set_launch(h, block, grid, remap, links_per_lane=1):
@@ -473,8 +491,14 @@ class Ensemble:
         except Exception:
             pass
 
-    def run(self, nsweeps, seed, plaq=True, poly=True):
-        return su2_ensemble_run(self.h, self.n, nsweeps, seed, plaq, poly)
+    def run(self, nsweeps, seed, plaq=True, poly=True, measure_every=1):
+        return su2_ensemble_run(self.h, self.n, nsweeps, seed, plaq, poly, measure_every)
+
+    def trace_tries(self, enable=True):
+        su2_ensemble_trace_tries(self.h, enable)
+
+    def get_tries(self, i):
+        return su2_ensemble_get_tries(self.h, i, int(np.prod(self.dims[i])))
 
     def get_links(self, i):
         return su2_ensemble_get_links(self.h, i, int(np.prod(self.dims[i])))

@@ -46,6 +46,25 @@ def test_host_validation():
     assert su2._lib.su2_status_str(-7).decode().startswith("non-finite")
 
 
+def test_volume_cap_per_precision():
+    """Link offsets inside a (mu, parity) block are 32-bit byte offsets, so a
+    lattice holds at most 2^29 sites in binary32 and 2^28 in binary64; larger
+    extents are refused before anything is allocated."""
+    from paper_1010_4834_amd import su2
+    V29 = (64, 128, 128, 512)          # 2^29 sites
+    assert su2.su2_link_bytes(*V29, su2.F32) == 4 * (1 << 29) * 16
+    assert su2.su2_link_bytes(*V29, su2.F64) == 0
+    assert su2.su2_link_bytes(64, 128, 128, 256, su2.F64) == 4 * (1 << 28) * 32
+    assert su2.su2_link_bytes(128, 128, 128, 512, su2.F32) == 0   # 2^30 sites
+    for dims, prec in ((V29, su2.F64), ((128, 128, 128, 512), su2.F32)):
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_create(*dims, su2.COLD, 1, prec)
+        assert e.value.status == su2.EINVAL
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_ensemble_create([dims], [2.0], su2.HOT, 1, prec)
+        assert e.value.status == su2.EINVAL
+
+
 @pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU path")
 def test_no_device():
     from paper_1010_4834_amd import su2

@@ -36,23 +36,60 @@ def test_ensemble_fp64_parity(su2, orc):
     ens.close()
 
 
-def test_ensemble_fp32_c5_shapes(su2, orc):
+def fp32_ensemble_sweep_parity(su2, orc, ens, dims, betas, seed, sample, label):
+    """One binary32 sweep of the whole ensemble under its current launch
+    shape; each sampled lattice against the binary64 oracle run from the
+    library's own starting links with its lattice id and coupling, link by
+    link (parity_util.check_fp32_sweep: 1e-5, flips and conditioned links
+    counted), and the fused plaquette and Polyakov series against the oracle
+    on the GPU's binary32 links."""
+    from tests import parity_util
+    U0 = {i: ens.get_links(i) for i in sample}
+    ens.trace_tries(True)
+    P, L = ens.run(1, seed)
+    tot = {"flips": 0, "over_tol": 0, "downstream": 0, "conditioned": 0}
+    for i in sample:
+        d = dims[i]
+        O = U0[i].copy()
+        to = np.zeros(4 * O.shape[0], np.uint32)
+        orc.heatbath_sweep(d, O, betas[i], seed, 0, lat_id=i, ubits=23, trace=to)
+        G = ens.get_links(i)
+        r = parity_util.check_fp32_sweep(orc, d, betas[i], U0[i], G, O, ens.get_tries(i), to,
+                                         label=f"{label} lattice {i} ")
+        for k in tot:
+            tot[k] += r[k]
+        assert abs(P[i, 0] - orc.plaquette(d, G)[0]) < 1e-6, i
+        assert abs(L[i, 0] - orc.polyakov(d, G)) < 1e-6, i
+    print(f"{label} FP32 totals over {len(sample)} lattices: {tot}", flush=True)
+    ens.trace_tries(False)
+    return tot
+
+
+def test_ensemble_fp32_c5_link_parity(su2, orc):
     """The 64-lattice uneven ensemble (L in {8,12,16,24}, Nt in {4,6,8,L}),
-    FP32 links: 2 sweeps; every lattice's plaquette series against the FP64
-    oracle within the FP32 tolerance (flips allowed, reported)."""
+    binary32 links, one sweep under the autotuned launch shape: one lattice
+    of each of the 16 extent classes (spread over the lattice ids and
+    couplings) link by link against the binary64 oracle."""
     dims, betas = inputs.c5_shapes()
     ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=5, prec=su2.F32)
     su2.su2_ensemble_autotune(ens.h)
-    P, L = ens.run(2, 5)
-    worst = 0.0
-    for i in range(0, 64, 9):
-        U = orc.hot(dims[i], 5, lat_id=i).astype(np.float32).astype(np.float64)
-        for sw in range(2):
-            orc.heatbath_sweep(dims[i], U, betas[i], 5, sw, lat_id=i, ubits=23)
-        worst = max(worst, abs(P[i, 1] - orc.plaquette(dims[i], U)[0]))
-    print(f"C5 FP32 worst |dP| after 2 sweeps: {worst:.2e}")
-    assert worst < 1e-4
-    assert np.isfinite(P).all() and np.isfinite(L).all()
+    print("launch", su2.su2_ensemble_get_launch(ens.h))
+    sample = [c + 16 * (c % 4) for c in range(16)]
+    assert sorted({dims[i] for i in sample}) == sorted(set(dims))
+    fp32_ensemble_sweep_parity(su2, orc, ens, dims, betas, 5, sample, "C5")
+    ens.close()
+
+
+def test_ensemble_fp32_c3_link_parity(su2, orc):
+    """The C3 beta scan at full size (16 x 32^3 x 4, beta in [2.1, 2.5], hot
+    start seed 3), binary32, one sweep under the autotuned launch shape:
+    lattices 0, 7 and 15 link by link against the binary64 oracle."""
+    dims = [(32, 32, 32, 4)] * 16
+    betas = inputs.c3_betas()
+    ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=3, prec=su2.F32)
+    su2.su2_ensemble_autotune(ens.h)
+    print("launch", su2.su2_ensemble_get_launch(ens.h))
+    fp32_ensemble_sweep_parity(su2, orc, ens, dims, betas, 3, (0, 7, 15), "C3")
     ens.close()
 
 
@@ -131,9 +168,11 @@ def test_measuring_does_not_change_the_chain(su2, prec):
 
 @pytest.mark.parametrize("prec", ["F64", "F32"])
 def test_multi_sweep_graphs_match_direct_launches(su2, prec):
-    """21 sweeps replay two graphs of 8 sweeps and five single-sweep graphs;
-    links, plaquette and Polyakov series are bit for bit those of the same
-    sweeps launched one kernel at a time (SU2_NO_GRAPH)."""
+    """21 sweeps replay graphs of 16, 4 and 1 sweeps, 5 sweeps graphs of 4
+    and 1, and 37 sweeps measured every second sweep graphs of 8, 8 and 2
+    two-sweep units and one plain sweep; links, plaquette and Polyakov
+    series are bit for bit those of the same sweeps launched one kernel at a
+    time (SU2_NO_GRAPH)."""
     import os
     dims, betas = [(6, 4, 10, 6), (4, 4, 4, 8)], [2.3, 2.6]
     out = []
@@ -144,14 +183,15 @@ def test_multi_sweep_graphs_match_direct_launches(su2, prec):
             ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=9, prec=getattr(su2, prec))
             P, L = ens.run(21, 9)
             P2, L2 = ens.run(5, 9)     # the counter continues across runs
-            out.append((P, L, P2, L2, [ens.get_links(i) for i in range(len(dims))]))
+            P3, L3 = ens.run(37, 9, measure_every=2)
+            out.append((P, L, P2, L2, P3, L3, [ens.get_links(i) for i in range(len(dims))]))
             ens.close()
         finally:
             os.environ.pop("SU2_NO_GRAPH", None)
     (a, b) = out
-    for x, y in zip(a[:4], b[:4]):
+    for x, y in zip(a[:6], b[:6]):
         assert np.array_equal(x, y)
-    for x, y in zip(a[4], b[4]):
+    for x, y in zip(a[6], b[6]):
         assert np.array_equal(x, y)
 
 

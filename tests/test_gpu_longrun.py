@@ -5,9 +5,10 @@ the same mean plaquette and mean |Polyakov loop| within three standard
 deviations of the combined binned jackknife errors.
 
 Sizes are reduced stand-ins for the production workloads so that the
-serial oracle finishes in seconds: 10^4 at beta = 2.3 (plaquette) and
+serial oracle finishes in about a minute: 10^4 at beta = 2.3 (plaquette),
 8^3 x 4 at beta = 2.2 and 2.45 (either side of the Nt = 4 transition) for
-the Polyakov loop."""
+the Polyakov loop, and a four-lattice 16^3 x 4 beta scan across the
+transition advanced as one ensemble (the C3 form)."""
 import sys
 import time
 
@@ -112,3 +113,34 @@ def test_polyakov_long_run(su2, orc, beta):
     agree(f"<P> beta {beta}", mean_err(Pg, discard, nbins), refP)
     agree(f"<|L|> beta {beta}", mean_err(np.abs(Lg), discard, nbins), refL)
     sys.stdout.flush()
+
+
+def test_beta_scan_across_the_transition(su2, orc):
+    """A reduced C3-like scan: four 16^3 x 4 lattices at beta = 2.2, 2.3, 2.4,
+    2.5 (either side of the Nt = 4 deconfinement point) advanced together as
+    one binary32 ensemble, against four independent serial oracle chains run
+    on host threads at once (the oracle is a C library called through ctypes,
+    which releases the interpreter lock).  <P> and <|L|> agree within three
+    combined binned-jackknife errors at every beta; the Polyakov loop
+    decorrelates slowly near the transition, hence long bins."""
+    from concurrent.futures import ThreadPoolExecutor
+    dims, betas = (16, 16, 16, 4), (2.2, 2.3, 2.4, 2.5)
+    n, discard, nbins = 2000, 200, 12
+
+    def oracle_chain(k):
+        t0 = time.perf_counter()
+        P, L = oracle_series(orc, dims, betas[k], 131 + k, n)
+        print(f"oracle chain beta {betas[k]}: {n} sweeps in {time.perf_counter() - t0:.1f} s", flush=True)
+        return P, L
+
+    with ThreadPoolExecutor(len(betas)) as ex:
+        fut = [ex.submit(oracle_chain, k) for k in range(len(betas))]
+        ens = su2.Ensemble([dims] * len(betas), list(betas), start=su2.HOT, seed=231, prec=su2.F32)
+        Pg, Lg = ens.run(n, 231)
+        ens.close()
+        ref = [f.result() for f in fut]
+    for k, b in enumerate(betas):
+        Po, Lo = ref[k]
+        agree(f"scan <P> beta {b}", mean_err(Pg[k], discard, nbins), mean_err(Po, discard, nbins))
+        agree(f"scan <|L|> beta {b}", mean_err(np.abs(Lg[k]), discard, nbins),
+              mean_err(np.abs(Lo), discard, nbins))

@@ -115,3 +115,28 @@ def test_c4_full_size_sampled(su2, orc):
     for R, T in ((1, 1), (2, 3), (12, 16)):
         assert abs(W[R - 1, T - 1] - orc.wilson_rt(dims, U, R, T, S)) < 1e-13, (R, T)
     lat.close()
+
+
+def test_c4_full_size_fp32(su2, orc):
+    """The C4 shape in binary32 (24^3 x 48, hot start seed 4): APE alpha =
+    0.7 x 25 and W(R <= 12, T <= 16) from the binary32 kernels (binary64
+    sums) against the binary64 oracle on the same binary32 links, at
+    (1,1), (2,3) and (12,16) within 2e-5.  The smeared links carry the
+    binary32 rounding of 25 chained Jacobi steps, each a normalised sum whose
+    norm can be small (the error is amplified by 1/|w|): 1e-4 for the worst
+    of the 2M links, 5e-6 for the 99.99th percentile."""
+    dims = (24, 24, 24, 48)
+    lat = su2.Lattice(dims, start=su2.HOT, seed=4, prec=su2.F32)
+    U = lat.get_links()
+    lat.ape_smear(0.7, 25)
+    W = lat.wilson_loops(12, 16)
+    S = orc.ape(dims, U, 0.7, 25)
+    dl = np.abs(lat.get_smeared() - S).max(axis=2)
+    ds, q = float(dl.max()), float(np.quantile(dl, 0.9999))
+    errs = {}
+    for R, T in ((1, 1), (2, 3), (12, 16)):
+        errs[(R, T)] = abs(W[R - 1, T - 1] - orc.wilson_rt(dims, U, R, T, S))
+    print(f"C4 binary32: smeared links max |dU| {ds:.2e}, 99.99% {q:.2e}; W errors {errs}")
+    assert ds < 1e-4 and q < 5e-6
+    assert max(errs.values()) < 2e-5
+    lat.close()
