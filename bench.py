@@ -6,12 +6,14 @@ is one heat-bath sweep (8 checkerboard substeps over all 4V links) followed
 by the mean plaquette, run through the batched path (the sweep and its
 measurement captured once in a HIP graph and replayed; batch of one).
 
-Prints ONE JSON line: value = link updates/s of the timed region, the
-roofline of the dominant kernel (the heat-bath substep; algorithmic traffic
-8 link transfers = 128 B per update, timed per launch with HIP events on the
-stream it runs on), the plain FP64 single-lattice form on the same GPU for
-comparison, and the serial FP64 oracle timed on the host cores on a bounded
-sample.
+Prints ONE JSON line: value = link updates/s of the timed region (the
+median of --reps repetitions of K steps), the roofline of the dominant kernel
+(the heat-bath substep; algorithmic traffic 8 link transfers = 128 B per
+update, timed per launch with HIP events stamped by the launch on the stream
+it runs on, in an eager pass after the timed region), the 64^4 control that
+exceeds the Infinity Cache, the plain FP64 single-lattice form on the same
+GPU and schedule for comparison, and the serial FP64 oracle timed on the
+host cores on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--config c1|c2|c2x2|c2x4|c3|c4|c5|control64]
 
@@ -33,6 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20
 
 # Bytes one heat-bath substep moves at 32^4 FP32, from rocprofv3 --pmc runs of
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the eight substeps
@@ -311,6 +314,102 @@ def fp64_loop(su2, dims_list, betas, seed, nsteps):
     return upd / secs, secs / nsteps
 
 
+def timed_runs(su2, torch, stream, ens, n, steps, seed, poly, reps, every=1):
+    """reps runs of `steps` sweeps with the series, each bracketed by device
+    synchronisation.  Returns the median repetition's seconds (the larger of
+    its wall and stream-event time), that repetition's event milliseconds and
+    the seconds of every repetition."""
+    res = []
+    for _ in range(max(1, reps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        su2.su2_ensemble_run(ens, n, steps, seed, True, poly, every)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gms = e0.elapsed_time(e1)
+        res.append((max(wall, gms * 1e-3), gms))
+    every = [r[0] for r in res]
+    res.sort()
+    return res[len(res) // 2] + (every,)
+
+
+def eager_event_pass(su2, ens, n, steps, seed, poly):
+    """K steps with graph replay off and every kernel timed with HIP events
+    (heat-bath launches stamp their own start and end)."""
+    import time as _t
+    su2.su2_ensemble_set_timing(ens, 1)
+    t0 = _t.perf_counter()
+    su2.su2_ensemble_run(ens, n, steps, seed, True, poly)
+    dt = _t.perf_counter() - t0
+    hb_ms, hb_n = su2.su2_ensemble_get_timing(ens, su2.K_HEATBATH)
+    po_ms, po_n = su2.su2_ensemble_get_timing(ens, su2.K_POLYAKOV)
+    rd_ms, rd_n = su2.su2_ensemble_get_timing(ens, su2.K_REDUCE)
+    su2.su2_ensemble_set_timing(ens, 0)
+    return {"hb_avg_us": 1e3 * hb_ms / hb_n, "poly_avg_us": 1e3 * po_ms / max(po_n, 1),
+            "reduce_avg_us": 1e3 * rd_ms / max(rd_n, 1), "reduce_n": rd_n, "ms_per_step": 1e3 * dt / steps}
+
+
+def fp64_form(su2, torch, stream, dims, beta, seed, args, value32):
+    """The plain FP64 single-lattice form: the same kernels instantiated for
+    binary64, one lattice, the library's default launch shape, on the same
+    schedule as the timed region (K steps of one sweep + plaquette, median
+    of the repetitions); the autotuned binary64 shape as a side figure."""
+    import numpy as np
+    V = int(np.prod(dims))
+    out = {}
+    for label, tune in (("default", False), ("autotuned", not args.no_tune)):
+        if label == "autotuned" and not tune:
+            continue
+        ens = su2.su2_ensemble_create([dims], [beta], su2.HOT, seed, su2.F64)
+        su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
+        if tune:
+            su2.su2_ensemble_autotune(ens)
+        launch = su2.su2_ensemble_get_launch(ens)
+        su2.su2_ensemble_run(ens, 1, 5, seed, True, False)
+        k64 = max(10, args.steps)
+        secs, _, _ = timed_runs(su2, torch, stream, ens, 1, k64, seed, False, 3)
+        ev = eager_event_pass(su2, ens, 1, max(5, k64 // 4), seed, False)
+        su2.su2_ensemble_destroy(ens)
+        v64 = 4 * V * k64 / secs
+        out[label] = {"value": v64, "ms_per_step": 1e3 * secs / k64, "steps": k64,
+                      "hb_avg_launch_us": ev["hb_avg_us"],
+                      "hb_GBs": (V // 2) * 256 / (ev["hb_avg_us"] * 1e-6) / 1e9,
+                      "launch": dict(zip(("block", "grid", "xcd_remap", "links_per_lane"), launch)),
+                      "speedup_fp32_batched": value32 / v64}
+    out["form"] = ("same kernels in binary64, one lattice, same schedule (one sweep + plaquette per step, "
+                   "graph replay), median of 3 repetitions")
+    return out
+
+
+def control64(su2, torch, stream, launch, seed, args):
+    """The 64^4 binary32 lattice (1 GiB of links, four times the 256 MB
+    Infinity Cache) at the 32^4 launch shape: steps of one sweep + plaquette
+    and the heat-bath launch time, the HBM-bound figure."""
+    dims, beta = (64, 64, 64, 64), 2.6
+    V = 64 ** 4
+    ens = su2.su2_ensemble_create([dims], [beta], su2.HOT, seed, su2.F32)
+    su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
+    su2.su2_ensemble_set_launch(ens, *launch)
+    su2.su2_ensemble_run(ens, 1, 2, seed, True, False)
+    k = max(4, args.steps // 4)
+    secs, _, _ = timed_runs(su2, torch, stream, ens, 1, k, seed, False, 3)
+    ev = eager_event_pass(su2, ens, 1, 3, seed, False)
+    su2.su2_ensemble_destroy(ens)
+    hb_bytes = (V // 2) * 128
+    ach = hb_bytes / (ev["hb_avg_us"] * 1e-6) / 1e9
+    traffic = None
+    if kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]:
+        traffic = HB_TRAFFIC.get("control64", {}).get(tuple(launch))
+    return {"workload": "64^4, beta=2.6, hot start, binary32, 1 sweep + plaquette per step, 32^4 launch shape",
+            "value": 4 * V * k / secs, "ms_per_step": 1e3 * secs / k, "steps": k,
+            "step_frac": 4 * V * 128 / (secs / k) / 1e9 / HBM_PEAK_GBS,
+            "avg_launch_us": ev["hb_avg_us"], "bytes_per_launch": hb_bytes, "achieved": ach,
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +427,9 @@ def main():
                     help="host threads for the all-core oracle figure (0: min(16, cores))")
     ap.add_argument("--launch", default=None,
                     help="block,grid,xcd_remap,links_per_lane (skips tuning)")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed repetitions of K steps; value is the median repetition")
+    ap.add_argument("--no-control", action="store_true", help="skip the 64^4 control in the c2 line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
@@ -361,29 +463,18 @@ def main():
     block, grid, remap, nl = su2.su2_ensemble_get_launch(ens)
     su2.su2_ensemble_run(ens, n, args.warmup, seed, True, cfg["poly"])
 
-    # ---- timed region: K steps, graph replay, one D2H of the series ----
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    P, L = su2.su2_ensemble_run(ens, n, args.steps, seed, True, cfg["poly"])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    secs = max(wall, gpu_ms * 1e-3)
+    # ---- timed region: reps x K steps (graph replay, the series stay on the
+    # device until the end of each run); value from the median repetition ----
+    secs, gpu_ms, rep_secs = timed_runs(su2, torch, stream, ens, n, args.steps, seed, cfg["poly"], args.reps)
     value = updates_per_step * args.steps / secs
+    P, _ = su2.su2_ensemble_run(ens, n, 1, seed, True, cfg["poly"])
     if not (np.isfinite(P).all() and (P > 0).all() and (P < 1).all()):
         raise RuntimeError("plaquette series invalid")
 
-    # ---- dominant kernel: every heat-bath launch bracketed by HIP events ----
-    su2.su2_ensemble_set_timing(ens, 1)
-    su2.su2_ensemble_run(ens, n, args.steps, seed, True, cfg["poly"])
-    hb_ms, hb_n = su2.su2_ensemble_get_timing(ens, su2.K_HEATBATH)
-    po_ms, po_n = su2.su2_ensemble_get_timing(ens, su2.K_POLYAKOV)
-    rd_ms, rd_n = su2.su2_ensemble_get_timing(ens, su2.K_REDUCE)
-    su2.su2_ensemble_set_timing(ens, 0)
-    hb_avg_us = 1e3 * hb_ms / hb_n
+    # ---- dominant kernel: every heat-bath launch of an eager pass of K steps
+    # stamped with HIP events by the launch itself ----
+    ev = eager_event_pass(su2, ens, n, args.steps, seed, cfg["poly"])
+    hb_avg_us = ev["hb_avg_us"]
     traffic = None
     # grid 0 = one workgroup per tile: the tile count rounded up to a multiple of 8
     tiles = -(-(updates_per_step // 8) // (block * nl))
@@ -393,6 +484,7 @@ def main():
     link_b = 16
     hb_bytes = (updates_per_step // 8) * 8 * link_b   # per substep: V/2 updates x 128 B
     achieved = hb_bytes / (hb_avg_us * 1e-6) / 1e9
+    step_GBs = updates_per_step * 8 * link_b / (secs / args.steps) / 1e9
     tries, updates = su2.su2_ensemble_stats(ens)
     fp32_err = None
     if n == 1:
@@ -430,6 +522,7 @@ def main():
                      "frac": or_bytes / (or_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
     su2.su2_ensemble_destroy(ens)
 
+    resident = updates_per_step * link_b <= INFINITY_CACHE_BYTES
     out = {
         "metric": "heat-bath link updates/s + HBM GB/s fraction, FP32 batched vs FP64 at 32^4",
         "value": value,
@@ -451,54 +544,38 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_heatbath<float> (one checkerboard substep)",
-                     "bytes_per_launch": hb_bytes, "avg_launch_us": hb_avg_us},
-        "other_kernels_us": {"polyakov": 1e3 * po_ms / max(po_n, 1),
-                             "series_reduction_per_batch": 1e3 * rd_ms / max(rd_n, 1),
-                             "series_reduction_batches": rd_n},
+                     "bytes_per_launch": hb_bytes, "avg_launch_us": hb_avg_us,
+                     "avg_launch_source": "HIP events stamped by each heat-bath launch (its dispatch "
+                                          "start and end) in an eager pass of K steps after the timed "
+                                          "region; graph replay is off in that pass",
+                     "step_frac": step_GBs / HBM_PEAK_GBS,
+                     "links_in_infinity_cache": resident},
+        "timing": {"reps": args.reps, "rep_ms_per_step": [1e3 * t / args.steps for t in rep_secs],
+                   "gpu_event_ms_median_rep": gpu_ms,
+                   "eager_pass_ms_per_step": ev["ms_per_step"]},
+        "other_kernels_us": {"polyakov": ev["poly_avg_us"], "series_reduction_per_batch": ev["reduce_avg_us"],
+                             "series_reduction_batches": ev["reduce_n"]},
         "plaquette": "summed inside the odd heat-bath substeps (no separate pass)",
-        "step_GBs": updates_per_step * 8 * link_b / (secs / args.steps) / 1e9,
+        "step_GBs": step_GBs,
         "tries_per_update": tries / max(updates, 1),
         "fp32_error": fp32_err,
-        "gpu_event_ms": gpu_ms,
     }
     if overrelax:
         out["overrelax"] = overrelax
 
-    # ---- the plain FP64 single-lattice form on the same GPU ----
+    # ---- the plain FP64 single-lattice form on the same GPU and schedule ----
     if not args.no_fp64 and n == 1:
-        lat = su2.su2_create(*dims[0], su2.HOT, seed, su2.F64)
-        su2.su2_set_stream(lat, stream.cuda_stream)
-        if not args.no_tune:
-            su2.su2_autotune(lat, betas[0])
-        launch64 = su2.su2_get_launch(lat)
-        su2.su2_heatbath(lat, betas[0], 5, seed)
-        su2.su2_plaquette(lat)
-        k64 = max(10, args.steps // 4)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(k64):
-            su2.su2_heatbath(lat, betas[0], 1, seed)
-            su2.su2_plaquette(lat)
-        torch.cuda.synchronize()
-        s64 = time.perf_counter() - t0
-        su2.su2_set_timing(lat, 1)
-        for _ in range(k64):
-            su2.su2_heatbath(lat, betas[0], 1, seed)
-        hb64_ms, hb64_n = su2.su2_get_timing(lat, su2.K_HEATBATH)
-        su2.su2_destroy(lat)
-        v64 = updates_per_step * k64 / s64
-        hb64_us = 1e3 * hb64_ms / hb64_n
-        out["fp64_plain"] = {"value": v64, "ms_per_step": 1e3 * s64 / k64, "steps": k64,
-                             "hb_avg_launch_us": hb64_us,
-                             "launch": dict(zip(("block", "grid", "xcd_remap", "links_per_lane"), launch64)),
-                             "hb_GBs": (updates_per_step // 8) * 256 / (hb64_us * 1e-6) / 1e9,
-                             "speedup_fp32_batched": value / v64}
+        out["fp64_plain"] = fp64_form(su2, torch, stream, dims[0], betas[0], seed, args, value)
 
     if not args.no_fp64 and n > 1:
         v64, s64 = fp64_loop(su2, dims, betas, seed, max(5, args.steps // 20))
         out["fp64_plain_loop"] = {"value": v64, "ms_per_step": 1e3 * s64,
                                   "form": "plain FP64 single-lattice calls looped over the lattices",
                                   "speedup_fp32_batched": value / v64}
+
+    # ---- the HBM-bound control: 64^4 (1 GiB of links, beyond the cache) ----
+    if args.config == "c2" and not args.no_control:
+        out["control64"] = control64(su2, torch, stream, (block, grid, remap, nl), seed, args)
 
     if (args.config == "c2" or args.copy_probe) and not args.no_copy_probe:
         out["copy_probe_GBs"] = copy_probe(torch)

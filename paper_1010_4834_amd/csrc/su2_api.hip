@@ -94,14 +94,17 @@ struct su2_ensemble_s {
     int fin_chunks = 1;             // workgroups per lattice in the final reduction
     double *res = nullptr;   // device scratch for single results
     double *hres = nullptr;  // pinned host mirror of res
-    double *ser_plaq = nullptr, *ser_poly = nullptr;
-    int ser_cap = 0;
 
     int ser_C = 1;                  // chunks per (lattice, sweep) of the series reduction
     double *ser_chunk = nullptr;    // their (hi, lo) pairs
-    double *hser = nullptr;         // pinned host staging of the series
+    // Series values and the error word are written by kernels straight into
+    // mapped, coherent pinned host memory (device addresses dser, derr), so
+    // a call ends with one synchronisation and no copy.
+    double *hser = nullptr, *dser = nullptr;
     size_t hser_cap = 0;            // doubles
-    unsigned *herr = nullptr;       // pinned host copy of the error word
+    double *run_plaq = nullptr, *run_poly = nullptr;  // device targets of the current run
+    int run_nm = 0;
+    unsigned *herr = nullptr, *derr = nullptr;
 
     hipStream_t own = nullptr, user = nullptr;
     // captured sweep graphs by (measurement mask, sweeps per measurement,
@@ -202,6 +205,24 @@ su2_status dalloc(su2_ensemble_s *E, P **p, size_t bytes) {
         return SU2_ENOMEM;
     }
     if (e != hipSuccess) { E->failed = true; return SU2_EDEVICE; }
+    return SU2_OK;
+}
+
+// Mapped, coherent pinned host memory of `bytes` and its device address.
+su2_status host_mapped(su2_ensemble_s *E, void **host, void **dev, size_t bytes) {
+    (void)E;
+    *host = *dev = nullptr;
+    if (hipHostMalloc(host, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        *host = nullptr;
+        return SU2_ENOMEM;
+    }
+    if (hipHostGetDevicePointer(dev, *host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(*host);
+        *host = nullptr;
+        return SU2_ENOMEM;
+    }
     return SU2_OK;
 }
 
@@ -424,7 +445,8 @@ su2_status upload_state(su2_ensemble_s *E) {
 // hits since the last report) is read.  A non-zero word is this call's
 // ENUMERIC and is cleared, so the next call starts clean.
 su2_status finish(su2_ensemble_s *E) {
-    HIPCHK(hipMemcpyAsync(E->herr, &E->st->err, sizeof(unsigned), hipMemcpyDeviceToHost, E->stream()));
+    su2::launch_err_to_host(E->st, E->derr, E->stream());
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(E->stream()));
     if (*E->herr == 0u) return SU2_OK;
     *E->herr = 0u;
@@ -434,6 +456,27 @@ su2_status finish(su2_ensemble_s *E) {
 }
 
 void invalidate_measure_buffers(su2_ensemble_s *E) { E->sm_cur = -1; }
+
+// Descriptor of lattice l with extents d, whose links start at link `off`
+// of the buffer and whose sites at site `sites` of the ensemble.
+void fill_desc(LatDesc &D, const int *d, int l, long long off, long long sites, double beta) {
+    std::memset(&D, 0, sizeof(D));
+    for (int k = 0; k < 4; ++k) D.n[k] = d[k];
+    const long long V = (long long)d[0] * d[1] * d[2] * d[3];
+    D.hx = d[0] / 2;
+    D.vh = (int)(V / 2);
+    D.ns = d[0] * d[1] * d[2];
+    D.lat_id = l;
+    D.off = off;
+    D.soff = 3 * sites;
+    D.toff = off;
+    D.inv_hx = recip_up(D.hx);
+    D.inv_nx = recip_up(d[0]);
+    D.inv_ny = recip_up(d[1]);
+    D.inv_nz = recip_up(d[2]);
+    D.beta = beta;
+    D.betaf = (float)beta;
+}
 
 // ---- creation ----------------------------------------------------------------
 su2_status create_common(int n, const int *dims, const double *betas, su2_start start, uint64_t seed,
@@ -450,23 +493,8 @@ su2_status create_common(int n, const int *dims, const double *betas, su2_start 
     long long off = 0, sites = 0;
     for (int l = 0; l < n; ++l) {
         const int *d = dims + 4 * l;
-        LatDesc &D = E->hdesc[l];
-        std::memset(&D, 0, sizeof(D));
-        for (int k = 0; k < 4; ++k) D.n[k] = d[k];
+        fill_desc(E->hdesc[l], d, l, off, sites, betas ? betas[l] : 0.0);
         const long long V = (long long)d[0] * d[1] * d[2] * d[3];
-        D.hx = d[0] / 2;
-        D.vh = (int)(V / 2);
-        D.ns = d[0] * d[1] * d[2];
-        D.lat_id = l;
-        D.off = off;
-        D.soff = 3 * sites;
-        D.toff = off;
-        D.inv_hx = recip_up(D.hx);
-        D.inv_nx = recip_up(d[0]);
-        D.inv_ny = recip_up(d[1]);
-        D.inv_nz = recip_up(d[2]);
-        D.beta = betas ? betas[l] : 0.0;
-        D.betaf = (float)D.beta;
         off += 4 * V;
         sites += V;
     }
@@ -488,10 +516,7 @@ su2_status create_common(int n, const int *dims, const double *betas, su2_start 
         E->hres = nullptr;
         return SU2_ENOMEM;
     }
-    if (hipHostMalloc((void **)&E->herr, sizeof(unsigned) * 16, hipHostMallocDefault) != hipSuccess) {
-        E->herr = nullptr;
-        return SU2_ENOMEM;
-    }
+    if (host_mapped(E, (void **)&E->herr, (void **)&E->derr, sizeof(unsigned) * 16) != SU2_OK) return SU2_ENOMEM;
     E->hst.seed = seed;
     E->hst.sweep = 0;
     E->hst.run_base = 0;
@@ -517,7 +542,7 @@ void destroy_common(su2_ensemble_s *E) {
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
     void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->mtiles_z, E->st, E->tries_part, E->part_plaq,
-                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_plaq, E->ser_poly, E->ser_chunk,
+                    E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_chunk,
                     E->sm[0], E->sm[1], E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -574,7 +599,7 @@ su2_status series_batch(su2_ensemble_s *E, int meas, int u0, int nmeas, hipStrea
     Timed r(E, SU2_K_REDUCE, s);
     su2::launch_series(E->ddesc, E->n, (meas & 1) ? E->part_hb : nullptr, 12 * (long long)E->nmtiles,
                        (meas & 2) ? E->part_poly : nullptr, 2 * (long long)E->nstiles, u0 % E->nslots,
-                       E->nslots, nmeas, E->ser_C, E->ser_chunk, E->ser_plaq, E->ser_poly, E->ser_cap, u0, s);
+                       E->nslots, nmeas, E->ser_C, E->ser_chunk, E->run_plaq, E->run_poly, E->run_nm, u0, s);
     r.done(s);
     HIPCHK(hipGetLastError());
     return SU2_OK;
@@ -656,26 +681,15 @@ su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every) {
     return SU2_OK;
 }
 
-// Device series of nm measurements per lattice and their pinned host
-// staging.
+// Host staging of the series of nm measurements per lattice and both
+// observables (mapped pinned memory, written by the series kernels).
 su2_status ensure_series(su2_ensemble_s *E, int nm) {
-    if (nm > E->ser_cap) {
-        int cap = 64;
-        while (cap < nm) cap *= 2;
-        CHK(dalloc(E, &E->ser_plaq, sizeof(double) * (size_t)cap * E->n));
-        CHK(dalloc(E, &E->ser_poly, sizeof(double) * (size_t)cap * E->n));
-        E->ser_cap = cap;
-    }
     const size_t need = 2 * (size_t)nm * E->n;
     if (need > E->hser_cap) {
         if (E->hser) (void)hipHostFree(E->hser);
-        E->hser = nullptr;
+        E->hser = E->dser = nullptr;
         E->hser_cap = 0;
-        if (hipHostMalloc((void **)&E->hser, sizeof(double) * need, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            E->hser = nullptr;
-            return SU2_ENOMEM;
-        }
+        CHK(host_mapped(E, (void **)&E->hser, (void **)&E->dser, sizeof(double) * need));
         E->hser_cap = need;
     }
     return SU2_OK;
@@ -1019,15 +1033,13 @@ su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, int measure_every, uint
     E->hst.seed = seed;
     E->hst.run_base = E->hst.sweep;
     CHK(upload_state(E));
+    // the series kernels write measurement k of lattice l to [l * nm + k]
+    E->run_plaq = E->dser;
+    E->run_poly = E->dser + (size_t)nm * E->n;
+    E->run_nm = nm;
     CHK(run_sweeps(E, nsweeps, nm > 0 ? meas : 0, measure_every));
     hipStream_t s = E->stream();
-    // both series into the pinned staging, then one synchronisation
-    for (int m = 0; m < 2 && nm > 0; ++m) {
-        if (!(m == 0 ? plaq : poly)) continue;
-        HIPCHK(hipMemcpy2DAsync(E->hser + (size_t)m * nm * E->n, sizeof(double) * nm,
-                                m == 0 ? E->ser_plaq : E->ser_poly, sizeof(double) * E->ser_cap,
-                                sizeof(double) * nm, E->n, hipMemcpyDeviceToHost, s));
-    }
+    (void)s;
     const su2_status st = finish(E);
     if (st == SU2_EDEVICE) return st;
     for (int m = 0; m < 2 && nm > 0; ++m) {

@@ -70,6 +70,8 @@ void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp
 void launch_set_state(DevState *st, unsigned long long seed, unsigned sweep, unsigned run_base, hipStream_t s);
 // Zero the error word.
 void launch_clear_err(DevState *st, hipStream_t s);
+// Copy the error word to `out` (mapped host memory).
+void launch_err_to_host(const DevState *st, unsigned *out, hipStream_t s);
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s);
 void launch_wlines(const KArgs &a, bool f32, const void *sp, int sp_raw, int Rmax, void *sl, int block,

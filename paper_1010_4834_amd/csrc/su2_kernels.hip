@@ -766,6 +766,8 @@ __global__ void k_set_state(DevState *st, unsigned long long seed, unsigned swee
 
 __global__ void k_clear_err(DevState *st) { st->err = 0u; }
 
+__global__ void k_err_to_host(const DevState *st, unsigned *out) { *out = st->err; }
+
 // ---------------------------------------------------------------------------
 // APE smearing step (paper Sec. 2, APE equation) of the spatial links, all
 // at once from the previous step: U' = normalise[(1-alpha) U + (alpha/4)
@@ -1148,6 +1150,10 @@ void launch_set_state(DevState *st, unsigned long long seed, unsigned sweep, uns
 }
 
 void launch_clear_err(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(1), 0, s, st); }
+
+void launch_err_to_host(const DevState *st, unsigned *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_err_to_host, dim3(1), dim3(1), 0, s, st, out);
+}
 
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,

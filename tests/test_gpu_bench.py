@@ -1,7 +1,7 @@
 """The benchmark's one JSON line keeps its contract: a short default run
 (32^4, a fixed launch shape, a few steps) in a child process prints one line
-with the metric, the whole-job value, the roofline of the heat-bath kernel
-and the serial oracle baseline."""
+with the metric, the whole-job value, the roofline of the heat-bath kernel,
+the 64^4 control, the binary64 form and the serial oracle baseline."""
 import json
 import os
 import subprocess
@@ -34,4 +34,8 @@ def test_bench_json_contract():
     assert rf["traffic"] is None or rf["traffic"] > rf["bytes_per_launch"]
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["sample"]
-    assert d["overrelax"]["frac"] > 0 and d["fp64_plain"]["value"] > 0
+    assert rf["avg_launch_source"] and 0 < rf["step_frac"] < 1 and rf["links_in_infinity_cache"] is True
+    assert len(d["timing"]["rep_ms_per_step"]) == 5
+    assert d["overrelax"]["frac"] > 0 and d["fp64_plain"]["default"]["value"] > 0
+    c = d["control64"]
+    assert c["avg_launch_us"] > 0 and 0 < c["frac"] < 1 and c["bytes_per_launch"] == 64 ** 4 // 2 * 128

@@ -124,7 +124,8 @@ def test_c4_full_size_fp32(su2, orc):
     (1,1), (2,3) and (12,16) within 2e-5.  The smeared links carry the
     binary32 rounding of 25 chained Jacobi steps, each a normalised sum whose
     norm can be small (the error is amplified by 1/|w|): 1e-4 for the worst
-    of the 2M links, 5e-6 for the 99.99th percentile."""
+    of the 2M links, and the one-sweep per-link tolerance 1e-5 for the
+    99.99th percentile."""
     dims = (24, 24, 24, 48)
     lat = su2.Lattice(dims, start=su2.HOT, seed=4, prec=su2.F32)
     U = lat.get_links()
@@ -137,6 +138,6 @@ def test_c4_full_size_fp32(su2, orc):
     for R, T in ((1, 1), (2, 3), (12, 16)):
         errs[(R, T)] = abs(W[R - 1, T - 1] - orc.wilson_rt(dims, U, R, T, S))
     print(f"C4 binary32: smeared links max |dU| {ds:.2e}, 99.99% {q:.2e}; W errors {errs}")
-    assert ds < 1e-4 and q < 5e-6
+    assert ds < 1e-4 and q < 1e-5
     assert max(errs.values()) < 2e-5
     lat.close()
