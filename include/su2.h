@@ -240,6 +240,31 @@ su2_status su2_autotune(su2_lattice lat, double beta);
 su2_status su2_set_timing(su2_lattice lat, int enable);
 su2_status su2_get_timing(su2_lattice lat, su2_kernel_kind kind, double *ms, int64_t *launches);
 
+/* ---- allocation-free heat bath ---------------------------------------- */
+
+/* For callers that cannot allocate device memory or synchronise: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * nsweeps heat-bath sweeps, exactly those of su2_heatbath (bit for bit the
+ * same links for the same links, beta, seed and sweep counter; hybrid
+ * sampler), of ONE lattice held by the caller in device memory in the
+ * native layout of su2_device_links (device_links, su2_link_bytes bytes,
+ * updated in place), enqueued on hip_stream (NULL: the null stream) of the
+ * current device.  `sweep` is the Philox sweep word of the first sweep (the
+ * caller keeps the counter: the next call continues with sweep + nsweeps).
+ * Allocates nothing and does not synchronise: the state, descriptor, tile
+ * list and try counters live in a fixed device array of 4 MiB + 512 B per
+ * GPU, held until the process ends, so lattices are limited to 2^27 sites
+ * (EINVAL beyond; also EINVAL for the arguments su2_create / su2_heatbath
+ * refuse or a NULL device_links).  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and must be ordered by the caller.  device_err (nullable, device memory)
+ * receives the count of non-finite staples and try-cap hits of this call
+ * (the affected links are NaN).  ENODEV without a current device, EDEVICE
+ * if a launch fails. */
+su2_status su2_heatbath_noalloc(void *device_links, int Nx, int Ny, int Nz, int Nt, su2_prec prec,
+                                double beta, int nsweeps, uint64_t seed, uint32_t sweep,
+                                uint32_t *device_err, void *hip_stream);
+
 /* ---- ensembles of independent lattices -------------------------------- */
 
 /* n independent lattices of uneven sizes and couplings that advance in the

@@ -949,10 +949,123 @@ su2_status set_timing_common(su2_ensemble_s *E, int enable) {
     return SU2_OK;
 }
 
+// ---- allocation-free heat bath ---------------------------------------------------
+// The state, descriptor, tile list and per-tile try counters of
+// su2_heatbath_noalloc live in one file-scope device array (each GPU holds
+// its own copy): 512 header bytes (DevState at 0, LatDesc at 256), then
+// NOALLOC_MAX_TILES tiles and as many try counters.  Tiles of 256 half-sites,
+// so lattices up to 2^27 sites fit.
+constexpr int NOALLOC_BLOCK = 256;
+constexpr long long NOALLOC_MAX_SITES = 1LL << 27;
+constexpr int NOALLOC_MAX_TILES = (int)(NOALLOC_MAX_SITES / 2 / NOALLOC_BLOCK);
+constexpr size_t NOALLOC_HDR = 512;
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_HDR + (size_t)NOALLOC_MAX_TILES * (sizeof(Tile) + sizeof(unsigned long long));
+static_assert(sizeof(DevState) <= 256 && sizeof(LatDesc) <= 256, "scratch header layout");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+unsigned char *g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev`, taken once per device with
+// that device current (the caller's).  In host code the array's name is only
+// a host-side stand-in; kernels get this address.
+su2_status scratch_of(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return SU2_ENODEV;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SU2_EDEVICE;
+        }
+        g_scratch[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch[dev];
+    return SU2_OK;
+}
+
+// Per call: descriptor and state into the header, tiles (0, 256 i), try
+// counters zeroed; a kernel, so the call stays capturable.
+__global__ void k_noalloc_setup(unsigned char *sc, LatDesc d, unsigned long long seed, unsigned sweep, int ntiles) {
+    Tile *tiles = reinterpret_cast<Tile *>(sc + NOALLOC_HDR);
+    unsigned long long *tries = reinterpret_cast<unsigned long long *>(tiles + NOALLOC_MAX_TILES);
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < ntiles) {
+        tiles[i] = make_int2(0, i * NOALLOC_BLOCK);
+        tries[i] = 0ull;
+    }
+    if (i == 0) {
+        DevState *st = reinterpret_cast<DevState *>(sc);
+        st->seed = seed;
+        st->sweep = sweep;
+        st->next = sweep;
+        st->run_base = sweep;
+        st->err = 0u;
+        *reinterpret_cast<LatDesc *>(sc + 256) = d;
+    }
+}
+
+__global__ void k_noalloc_err(const unsigned char *sc, uint32_t *out) {
+    *out = reinterpret_cast<const DevState *>(sc)->err;
+}
+
 }  // namespace
 
 // ============================================================================
 extern "C" {
+
+su2_status su2_heatbath_noalloc(void *device_links, int Nx, int Ny, int Nz, int Nt, su2_prec prec, double beta,
+                                int nsweeps, uint64_t seed, uint32_t sweep, uint32_t *device_err,
+                                void *hip_stream) {
+    const int d[4] = {Nx, Ny, Nz, Nt};
+    if (!device_links || (prec != SU2_F32 && prec != SU2_F64) || !dims_ok(d, prec == SU2_F32)) return SU2_EINVAL;
+    if ((long long)Nx * Ny * Nz * Nt > NOALLOC_MAX_SITES) return SU2_EINVAL;
+    if (!(beta >= 0.0) || !std::isfinite(beta) || nsweeps < 0) return SU2_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return SU2_ENODEV;
+    }
+    unsigned char *sc = nullptr;
+    CHK(scratch_of(dev, &sc));
+    LatDesc D;
+    fill_desc(D, d, 0, 0, 0, beta);
+    const int ntiles = (D.vh + NOALLOC_BLOCK - 1) / NOALLOC_BLOCK;
+    D.tile0 = D.mtile0 = 0;
+    D.ntile = D.nmtile = ntiles;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, sc, D,
+                       (unsigned long long)seed, (unsigned)sweep, ntiles);
+    KArgs a{};
+    a.desc = reinterpret_cast<const LatDesc *>(sc + 256);
+    a.tiles = reinterpret_cast<const Tile *>(sc + NOALLOC_HDR);
+    a.ntiles = ntiles;
+    a.xcd_remap = 1;
+    a.links = device_links;
+    a.st = reinterpret_cast<DevState *>(sc);
+    a.err = &a.st->err;
+    a.trace = nullptr;
+    a.tries_part = reinterpret_cast<unsigned long long *>(sc + NOALLOC_HDR + sizeof(Tile) * NOALLOC_MAX_TILES);
+    a.plaq_part = nullptr;
+    a.sampler = SU2_HYBRID;
+    a.advance = 1;
+    a.nslots = 0;
+    a.every = 1;
+    for (int k = 0; k < nsweeps; ++k)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int par = 0; par < 2; ++par)
+                su2::launch_heatbath(a, prec == SU2_F32, mu, par, 1, NOALLOC_BLOCK, 0, s, false, false);
+    if (device_err) hipLaunchKernelGGL(k_noalloc_err, dim3(1), dim3(1), 0, s, sc, device_err);
+    return hipGetLastError() == hipSuccess ? SU2_OK : SU2_EDEVICE;
+}
+
 
 const char *su2_status_str(su2_status st) {
     switch (st) {

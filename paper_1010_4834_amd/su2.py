@@ -77,6 +77,7 @@ _SIGS = {
     "su2_autotune": (_I, [_P, _D]),
     "su2_set_timing": (_I, [_P, _I]),
     "su2_get_timing": (_I, [_P, _I, _P, _P]),
+    "su2_heatbath_noalloc": (_I, [_P, _I, _I, _I, _I, _I, _D, _I, _U64, _U32, _P, _P]),
     "su2_ensemble_create": (_I, [_I, _P, _P, _I, _U64, _I, _P, _SZ, _PP]),
     "su2_ensemble_destroy": (_I, [_P]),
     "su2_ensemble_set_stream": (_I, [_P, _P]),
@@ -280,6 +281,14 @@ def su2_get_timing(h, kind):
     ms, n = C.c_double(), C.c_int64()
     _chk(_lib.su2_get_timing(h, kind, C.byref(ms), C.byref(n)), "su2_get_timing")
     return ms.value, n.value
+
+
+def su2_heatbath_noalloc(device_links, dims, prec, beta, nsweeps, seed, sweep=0, device_err=None, stream=None):
+    """Heat-bath sweeps of a caller-owned native link buffer (device pointer)
+    that allocate nothing and do not synchronise."""
+    nx, ny, nz, nt = (int(d) for d in dims)
+    _chk(_lib.su2_heatbath_noalloc(device_links, nx, ny, nz, nt, prec, beta, nsweeps, seed, sweep,
+                                   device_err, stream), "su2_heatbath_noalloc")
 
 
 def su2_ensemble_create(dims, betas, start, seed, prec, device_links=None, device_bytes=0):

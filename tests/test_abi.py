@@ -65,6 +65,22 @@ def test_volume_cap_per_precision():
         assert e.value.status == su2.EINVAL
 
 
+def test_noalloc_argument_checks():
+    """The allocation-free heat bath refuses bad arguments and lattices beyond
+    its fixed scratch (2^27 sites) before any device call."""
+    from paper_1010_4834_amd import su2
+    fake = 1 << 20        # never dereferenced: every case fails validation first
+    for args in (((256, 256, 256, 16), su2.F32, 2.3, 1),     # 2^28 sites
+                 ((8, 8, 8, 7), su2.F32, 2.3, 1), ((8, 8, 8, 8), 5, 2.3, 1),
+                 ((8, 8, 8, 8), su2.F32, -1.0, 1), ((8, 8, 8, 8), su2.F32, 2.3, -1)):
+        with pytest.raises(su2.SU2Error) as e:
+            su2.su2_heatbath_noalloc(fake, *args, 1)
+        assert e.value.status == su2.EINVAL, args
+    with pytest.raises(su2.SU2Error) as e:
+        su2.su2_heatbath_noalloc(None, (8, 8, 8, 8), su2.F32, 2.3, 1, 1)
+    assert e.value.status == su2.EINVAL
+
+
 @pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU path")
 def test_no_device():
     from paper_1010_4834_amd import su2
