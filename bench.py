@@ -386,13 +386,18 @@ def fp64_form(su2, torch, stream, dims, beta, seed, args, value32):
 
 def control64(su2, torch, stream, launch, seed, args):
     """The 64^4 binary32 lattice (1 GiB of links, four times the 256 MB
-    Infinity Cache) at the 32^4 launch shape: steps of one sweep + plaquette
-    and the heat-bath launch time, the HBM-bound figure."""
+    Infinity Cache) under its own autotuned launch shape (the 32^4 shape with
+    --no-tune or --launch): steps of one sweep + plaquette and the heat-bath
+    launch time, the HBM-bound figure."""
     dims, beta = (64, 64, 64, 64), 2.6
     V = 64 ** 4
     ens = su2.su2_ensemble_create([dims], [beta], su2.HOT, seed, su2.F32)
     su2.su2_ensemble_set_stream(ens, stream.cuda_stream)
-    su2.su2_ensemble_set_launch(ens, *launch)
+    if args.no_tune or args.launch:
+        su2.su2_ensemble_set_launch(ens, *launch)
+    else:
+        su2.su2_ensemble_autotune(ens)
+    launch = su2.su2_ensemble_get_launch(ens)
     su2.su2_ensemble_run(ens, 1, 2, seed, True, False)
     k = max(4, args.steps // 4)
     secs, _, _ = timed_runs(su2, torch, stream, ens, 1, k, seed, False, 3)
@@ -403,7 +408,8 @@ def control64(su2, torch, stream, launch, seed, args):
     traffic = None
     if kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]:
         traffic = HB_TRAFFIC.get("control64", {}).get(tuple(launch))
-    return {"workload": "64^4, beta=2.6, hot start, binary32, 1 sweep + plaquette per step, 32^4 launch shape",
+    return {"workload": "64^4, beta=2.6, hot start, binary32, 1 sweep + plaquette per step",
+            "launch": dict(zip(("block", "grid", "xcd_remap", "links_per_lane"), launch)),
             "value": 4 * V * k / secs, "ms_per_step": 1e3 * secs / k, "steps": k,
             "step_frac": 4 * V * 128 / (secs / k) / 1e9 / HBM_PEAK_GBS,
             "avg_launch_us": ev["hb_avg_us"], "bytes_per_launch": hb_bytes, "achieved": ach,
@@ -427,7 +433,7 @@ def main():
                     help="host threads for the all-core oracle figure (0: min(16, cores))")
     ap.add_argument("--launch", default=None,
                     help="block,grid,xcd_remap,links_per_lane (skips tuning)")
-    ap.add_argument("--reps", type=int, default=5,
+    ap.add_argument("--reps", type=int, default=7,
                     help="timed repetitions of K steps; value is the median repetition")
     ap.add_argument("--no-control", action="store_true", help="skip the 64^4 control in the c2 line")
     args = ap.parse_args()

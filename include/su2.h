@@ -222,7 +222,10 @@ su2_status su2_load(const char *path, su2_lattice *out);
  * multiple of 8), the tile mode (0: tiles round-robin over the XCDs; 1: each
  * XCD takes a contiguous share of the tile list; 2: as 1, with the heat-bath
  * tiles of every direction in (z, t, y, x) order, which modes 0 and 1 use for
- * the temporal direction only), and heat-bath links per lane (1, 2 or 4: a
+ * the temporal direction only; 3: as 1, with each lattice's heat-bath tiles
+ * in eight blocks -- (z half, t quarter) for mu < 3, (z quarter, y half) for
+ * mu = 3 -- so that an XCD's share reads fewer halo links), and heat-bath
+ * links per lane (1, 2 or 4: a
  * lane draws its links in one rejection loop).  Link updates do not depend
  * on it; reductions only in rounding.  EINVAL for other values. */
 su2_status su2_set_launch(su2_lattice lat, int block, int grid, int xcd_remap, int links_per_lane);

@@ -72,9 +72,12 @@ struct su2_ensemble_s {
     long long total_sites = 0;
 
     int block = 256, grid = 0, remap = 1, nl = 1;
-    std::vector<Tile> htiles, hstiles, hvtiles, hmtiles, hmtiles_z;
+    std::vector<Tile> htiles, hstiles, hvtiles, hmtiles, hmtiles_z, hmtiles_b, hmtiles_b3;
     Tile *tiles = nullptr, *stiles = nullptr, *vtiles = nullptr, *mtiles = nullptr;
     Tile *mtiles_z = nullptr;  // the heat-bath tiles of each lattice in (z, t, y, x) order
+    // tile mode 3: the heat-bath tiles in eight blocks per lattice, (z half,
+    // t quarter) for mu < 3 and (z quarter, y half) for mu = 3
+    Tile *mtiles_b = nullptr, *mtiles_b3 = nullptr;
     int ntiles = 0, nstiles = 0, nvtiles = 0, nmtiles = 0;
 
     void *links = nullptr;
@@ -252,7 +255,7 @@ KArgs kargs(su2_ensemble_s *E, int which = 0) {
     KArgs a;
     a.desc = E->ddesc;
     a.tiles = which == 0 ? E->tiles : which == 1 ? E->stiles : which == 2 ? E->vtiles
-            : which == 3 ? E->mtiles : E->mtiles_z;
+            : which == 3 ? E->mtiles : which == 4 ? E->mtiles_z : which == 5 ? E->mtiles_b : E->mtiles_b3;
     a.ntiles = which == 0 ? E->ntiles : which == 1 ? E->nstiles : which == 2 ? E->nvtiles : E->nmtiles;
     a.xcd_remap = E->remap != 0;
     a.links = E->links;
@@ -266,6 +269,14 @@ KArgs kargs(su2_ensemble_s *E, int which = 0) {
     a.nslots = 0;
     a.every = 1;
     return a;
+}
+
+// Heat-bath tile list of direction mu in the handle's tile mode: modes 0
+// and 1 lexicographic, with (z, t, y, x) order for mu = 3; mode 2 (z, t, y,
+// x) for every mu; mode 3 the XCD blocks.  All lists hold the same tiles.
+const Tile *hb_tiles(const su2_ensemble_s *E, int mu) {
+    if (E->remap == 3) return mu == 3 ? E->mtiles_b3 : E->mtiles_b;
+    return (mu == 3 || E->remap == 2) ? E->mtiles_z : E->mtiles;
 }
 
 void drop_graphs(su2_ensemble_s *E) {
@@ -352,6 +363,8 @@ su2_status build_tiles(su2_ensemble_s *E) {
     E->hvtiles.clear();
     E->hmtiles.clear();
     E->hmtiles_z.clear();
+    E->hmtiles_b.clear();
+    E->hmtiles_b3.clear();
     const int B = E->block;
     for (int l = 0; l < E->n; ++l) {
         LatDesc &d = E->hdesc[l];
@@ -371,14 +384,32 @@ su2_status build_tiles(su2_ensemble_s *E) {
         // XCD-aware walk gives each XCD a contiguous share of the list, which
         // in this order is a range of z over every t, so the temporal
         // neighbours of the mu = 3 substeps stay in that XCD's L2.
-        std::vector<std::pair<long long, Tile>> zt;
+        //
+        // Tile mode 3 gives each XCD (an eighth of the list) a block of the
+        // lattice that is thick in two directions other than the one being
+        // updated, so fewer staple links lie on its boundary: a slab four
+        // t-slices thick (32^4 in lexicographic order) reads a halo of four
+        // link classes times one face, about 14% of its links, a (z half,
+        // t quarter) block about 11%.  mu = 3 staples reach forward in t, so
+        // its blocks split z and y instead.
+        std::vector<std::pair<long long, Tile>> zt, bl, bl3;
         for (int i = d.mtile0; i < d.mtile0 + d.nmtile; ++i) {
             const long long cbs = E->hmtiles[i].y, row = cbs / d.hx;  // row = y + Ny (z + Nz t)
             const long long y = row % d.n[1], z = (row / d.n[1]) % d.n[2], t = row / ((long long)d.n[1] * d.n[2]);
-            zt.push_back({((z * d.n[3] + t) * d.n[1] + y) * d.hx + cbs % d.hx, E->hmtiles[i]});
+            const long long ztyx = ((z * d.n[3] + t) * d.n[1] + y) * d.hx + cbs % d.hx;
+            zt.push_back({ztyx, E->hmtiles[i]});
+            const long long b0 = (z * 2 / d.n[2]) * 4 + t * 4 / d.n[3];
+            const long long b3 = (z * 4 / d.n[2]) * 2 + y * 2 / d.n[1];
+            bl.push_back({(b0 << 40) + cbs, E->hmtiles[i]});
+            bl3.push_back({(b3 << 40) + ztyx, E->hmtiles[i]});
         }
-        std::sort(zt.begin(), zt.end(), [](const auto &u, const auto &v) { return u.first < v.first; });
+        const auto by_key = [](const auto &u, const auto &v) { return u.first < v.first; };
+        std::sort(zt.begin(), zt.end(), by_key);
+        std::sort(bl.begin(), bl.end(), by_key);
+        std::sort(bl3.begin(), bl3.end(), by_key);
         for (auto &e : zt) E->hmtiles_z.push_back(e.second);
+        for (auto &e : bl) E->hmtiles_b.push_back(e.second);
+        for (auto &e : bl3) E->hmtiles_b3.push_back(e.second);
     }
     E->ntiles = (int)E->htiles.size();
     E->nstiles = (int)E->hstiles.size();
@@ -389,6 +420,8 @@ su2_status build_tiles(su2_ensemble_s *E) {
     CHK(dalloc(E, &E->vtiles, sizeof(Tile) * E->nvtiles));
     CHK(dalloc(E, &E->mtiles, sizeof(Tile) * E->nmtiles));
     CHK(dalloc(E, &E->mtiles_z, sizeof(Tile) * E->nmtiles));
+    CHK(dalloc(E, &E->mtiles_b, sizeof(Tile) * E->nmtiles));
+    CHK(dalloc(E, &E->mtiles_b3, sizeof(Tile) * E->nmtiles));
     CHK(dalloc(E, &E->tries_part, sizeof(unsigned long long) * E->ntiles));
     CHK(dalloc(E, &E->part_plaq, sizeof(double) * 4 * E->ntiles));
     {   // series partials of up to nslots sweeps (about 64 MiB at most),
@@ -421,6 +454,10 @@ su2_status build_tiles(su2_ensemble_s *E) {
     HIPCHK(hipMemcpyAsync(E->vtiles, E->hvtiles.data(), sizeof(Tile) * E->nvtiles, hipMemcpyHostToDevice,
                           E->stream()));
     HIPCHK(hipMemcpyAsync(E->mtiles, E->hmtiles.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    HIPCHK(hipMemcpyAsync(E->mtiles_b, E->hmtiles_b.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
+                          E->stream()));
+    HIPCHK(hipMemcpyAsync(E->mtiles_b3, E->hmtiles_b3.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
                           E->stream()));
     HIPCHK(hipMemcpyAsync(E->mtiles_z, E->hmtiles_z.data(), sizeof(Tile) * E->nmtiles, hipMemcpyHostToDevice,
                           E->stream()));
@@ -541,7 +578,7 @@ void destroy_common(su2_ensemble_s *E) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : E->evpool) (void)hipEventDestroy(e);
-    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->mtiles_z, E->st, E->tries_part, E->part_plaq,
+    void *bufs[] = {E->ddesc, E->tiles, E->stiles, E->vtiles, E->mtiles, E->mtiles_z, E->mtiles_b, E->mtiles_b3, E->st, E->tries_part, E->part_plaq,
                     E->part_poly, E->part_hb, E->fin_cnt, E->fin_chunk, E->res, E->ser_chunk,
                     E->sm[0], E->sm[1], E->wl_s, E->wpart, E->trace};
     for (void *b : bufs)
@@ -568,8 +605,7 @@ su2_status enqueue_sweep(su2_ensemble_s *E, int meas, int every, hipStream_t s) 
     for (int mu = 0; mu < 4; ++mu)
         for (int par = 0; par < 2; ++par) {
             const bool plaq = (meas & 1) && par == 1 && mu >= 1;
-            // (z, t, y, x) tile order for mu = 3, and for every mu in tile mode 2
-            a.tiles = (mu == 3 || E->remap == 2) ? E->mtiles_z : E->mtiles;
+            a.tiles = hb_tiles(E, mu);
             Timed t(E, SU2_K_HEATBATH, s, true);
             su2::launch_heatbath(a, E->f32, mu, par, E->nl, E->block, E->grid, s, E->trace != nullptr, plaq,
                                  t.ev());
@@ -824,7 +860,7 @@ su2_status stats_common(su2_ensemble_s *E, uint64_t *tries, uint64_t *updates, d
 su2_status set_launch_common(su2_ensemble_s *E, int block, int grid, int remap, int nl) {
     if (block < 64 || block > 256 || (block & 63)) return SU2_EINVAL;
     if (grid < 0 || (grid & 7)) return SU2_EINVAL;
-    if (remap < 0 || remap > 2) return SU2_EINVAL;
+    if (remap < 0 || remap > 3) return SU2_EINVAL;
     if (nl != 1 && nl != 2 && nl != 4) return SU2_EINVAL;
     const bool reshape = block != E->block || nl != E->nl;
     E->grid = grid;
@@ -897,7 +933,7 @@ su2_status autotune_common(su2_ensemble_s *E) {
     for (int nl : nls)
         for (int b : blocks)
             for (int gm : gmul)
-                for (int rm = 0; rm < 3; ++rm) {
+                for (int rm = 0; rm < 4; ++rm) {
                     const int per_cu = gm >= 0 ? gm : su2::heatbath_blocks_per_cu(E->f32, nl, b);
                     const int g = per_cu > 0 ? per_cu * cus / 8 * 8 : 0;
                     if (gm < 0 && per_cu <= 0) continue;
@@ -1314,7 +1350,9 @@ su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int m
     hipStream_t s = E->stream();
     {
         Timed t(E, SU2_K_HEATBATH, s, true);
-        su2::launch_heatbath(kargs(E, (mu == 3 || E->remap == 2) ? 4 : 3), E->f32, mu, parity, E->nl, E->block, E->grid, s,
+        KArgs a = kargs(E, 3);
+        a.tiles = hb_tiles(E, mu);
+        su2::launch_heatbath(a, E->f32, mu, parity, E->nl, E->block, E->grid, s,
                              E->trace != nullptr, false, t.ev());
         t.done(s);
     }

@@ -778,38 +778,21 @@ __global__ void k_err_to_host(const DevState *st, unsigned *out) { *out = st->er
 // Grid row blockIdx.y = parity; a lane updates the three spatial links of
 // its site.
 
-// Smeared value of one link from its own link u and, for the two other
-// spatial directions nu in ascending order (k = 0, 1), the three links of
-// each of its two staples; the norm is the binary64 1/|w| (a smeared sum is
-// in general far from unit norm, so there is no near-group shortcut).
-template <class T>
-__device__ __forceinline__ Q<T> ape_update(const Q<T> &u, const Q<T> (&a1)[2], const Q<T> (&a2)[2],
-                                           const Q<T> (&a3)[2], const Q<T> (&b1)[2], const Q<T> (&b2)[2],
-                                           const Q<T> (&b3)[2], T alpha) {
-    Q<T> sum{T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        qmul_acc(sum, qmul(a1[k], a2[k]), qdag(a3[k]));
-        qmul_acc(sum, qmul(qdag(b1[k]), b2[k]), b3[k]);
-    }
-    const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
-    const Q<T> w{w0 * u.a + w1 * sum.a, w0 * u.b + w1 * sum.b, w0 * u.c + w1 * sum.c, w0 * u.d + w1 * sum.d};
-    const double wa = w.a, wb = w.b, wc = w.c, wd = w.d;
-    const double n2 = wa * wa + wb * wb + wc * wc + wd * wd;
-    Q<T> un = u;
-    if (n2 > 0.0) {
-        const double f = 1.0 / sqrt(n2);
-        un = Q<T>{(T)(wa * f), (T)(wb * f), (T)(wc * f), (T)(wd * f)};
-    }
-    return un;
-}
-
 // APE step of the three spatial links of one site (paper Sec. 2, APE
 // equation).  Their twelve staples touch 24 distinct links: the three own
-// links O, the forward links F[m][n] = U_m(x+n), the backward links
-// K[n] = U_n(x-n) and M[m][n] = U_m(x-n), and the diagonal links
-// D[n][m] = U_n(x+m-n); each is loaded once.  O and D have the site's
-// parity, the others the opposite one.
+// links O[m] = U_m(x) and the backward links K[n] = U_n(x-n), used by every
+// plane, and per spatial plane {m, n} (m < n) six links used by it alone,
+// each loaded once: F_mn = U_m(x+n), F_nm = U_n(x+m), M_mn = U_m(x-n),
+// M_nm = U_n(x-m), D_nm = U_n(x+m-n), D_mn = U_m(x+n-m).  Plane {m, n} adds
+// to the sum of direction m its forward staple U_n(x) U_m(x+n) U_n(x+m)^dag
+// and its backward staple U_n(x-n)^dag U_m(x-n) U_n(x-n+m), and the same
+// with m and n exchanged to the sum of direction n.  The planes run {0,1},
+// {0,2}, {1,2}, so every direction accumulates its two other directions in
+// ascending order, forward then backward.  Then U' = normalise[(1-alpha) U
+// + (alpha/4) sum], the norm in binary64: the hardware 1/sqrt estimate and
+// two Newton steps (each squares the relative error; after the second it is
+// below binary64 rounding).  A smeared sum is in general far from unit
+// norm, so there is no near-group shortcut.
 template <class T>
 __device__ __forceinline__ void ape_site(const LatDesc &d, const Blocks<T, 3> &Bs, const Blocks<T, 3> &Bd, int cb,
                                          int par, T alpha) {
@@ -821,35 +804,43 @@ __device__ __forceinline__ void ape_site(const LatDesc &d, const Blocks<T, 3> &B
         f[m] = step_fwd(d, S, m);
         b[m] = step_bwd(d, S, m);
     }
-    Q<T> O[3], K[3], F[3][3], M[3][3], D[3][3];
+    Q<T> O[3], K[3], sum[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         O[m] = lds_(Bs, m, par, (uint32_t)cb);
         K[m] = lds_(Bs, m, op, (uint32_t)(S.s + b[m]) >> 1);
-#pragma unroll
-        for (int n = 0; n < 3; ++n) {
-            if (n == m) continue;
-            F[m][n] = lds_(Bs, m, op, (uint32_t)(S.s + f[n]) >> 1);
-            M[m][n] = lds_(Bs, m, op, (uint32_t)(S.s + b[n]) >> 1);
-            D[m][n] = lds_(Bs, m, par, (uint32_t)(S.s + f[n] + b[m]) >> 1);
-        }
+        sum[m] = Q<T>{T(0), T(0), T(0), T(0)};
     }
 #pragma unroll
-    for (int mu = 0; mu < 3; ++mu) {
-        Q<T> a1[2], a2[2], a3[2], b1[2], b2[2], b3[2];
-        int k = 0;
+    for (int pl = 0; pl < 3; ++pl) {
+        const int m = pl == 2 ? 1 : 0, n = pl == 0 ? 1 : 2;
+        const Q<T> Fmn = lds_(Bs, m, op, (uint32_t)(S.s + f[n]) >> 1);
+        const Q<T> Fnm = lds_(Bs, n, op, (uint32_t)(S.s + f[m]) >> 1);
+        const Q<T> Mmn = lds_(Bs, m, op, (uint32_t)(S.s + b[n]) >> 1);
+        const Q<T> Mnm = lds_(Bs, n, op, (uint32_t)(S.s + b[m]) >> 1);
+        const Q<T> Dnm = lds_(Bs, n, par, (uint32_t)(S.s + f[m] + b[n]) >> 1);
+        const Q<T> Dmn = lds_(Bs, m, par, (uint32_t)(S.s + f[n] + b[m]) >> 1);
+        qmul_acc(sum[m], qmul(O[n], Fmn), qdag(Fnm));
+        qmul_acc(sum[m], qmul(qdag(K[n]), Mmn), Dnm);
+        qmul_acc(sum[n], qmul(O[m], Fnm), qdag(Fmn));
+        qmul_acc(sum[n], qmul(qdag(K[m]), Mnm), Dmn);
+    }
+    const T w0 = T(1) - alpha, w1 = T(0.25) * alpha;
 #pragma unroll
-        for (int nu = 0; nu < 3; ++nu) {
-            if (nu == mu) continue;
-            a1[k] = O[nu];
-            a2[k] = F[mu][nu];
-            a3[k] = F[nu][mu];
-            b1[k] = K[nu];
-            b2[k] = M[mu][nu];
-            b3[k] = D[nu][mu];
-            ++k;
+    for (int mu = 0; mu < 3; ++mu) {
+        const Q<T> &u = O[mu], &sm = sum[mu];
+        const Q<T> w{w0 * u.a + w1 * sm.a, w0 * u.b + w1 * sm.b, w0 * u.c + w1 * sm.c, w0 * u.d + w1 * sm.d};
+        const double wa = w.a, wb = w.b, wc = w.c, wd = w.d;
+        const double n2 = wa * wa + wb * wb + wc * wc + wd * wd;
+        Q<T> un = u;
+        if (n2 > 0.0) {
+            double y = __builtin_amdgcn_rsq(n2);
+            const double h = 0.5 * n2;
+            y = y * (1.5 - h * y * y);
+            y = y * (1.5 - h * y * y);
+            un = Q<T>{(T)(wa * y), (T)(wb * y), (T)(wc * y), (T)(wd * y)};
         }
-        sts_(Bd, mu, par, (uint32_t)cb, ape_update<T>(O[mu], a1, a2, a3, b1, b2, b3, alpha));
+        sts_(Bd, mu, par, (uint32_t)cb, un);
     }
 }
 

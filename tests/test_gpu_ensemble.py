@@ -119,7 +119,7 @@ def test_fused_plaquette_matches_standalone(su2, prec, tol):
     dims = [(8, 6, 4, 10), (6, 6, 6, 6)]
     p = getattr(su2, prec)
     ens = su2.Ensemble(dims, [2.4, 2.7], start=su2.HOT, seed=7, prec=p)
-    for launch in ((256, 0, 1, 1), (64, 16, 0, 2), (128, 0, 1, 4), (128, 0, 2, 1)):
+    for launch in ((256, 0, 1, 1), (64, 16, 0, 2), (128, 0, 1, 4), (128, 0, 2, 1), (64, 0, 3, 1)):
         su2.su2_ensemble_set_launch(ens.h, *launch)
         P, _ = ens.run(1, 7, plaq=True, poly=False)
         for i, d in enumerate(dims):

@@ -167,14 +167,15 @@ def test_full_size_c2_one_sweep(su2, orc, prec):
 
 
 def test_launch_shapes_bitwise(su2, orc):
-    """FP64 links do not depend on the launch shape, the tile mode or graph
-    replay."""
+    """FP64 links do not depend on the launch shape, the tile mode (all four)
+    or graph replay."""
     import os
     dims = (6, 4, 10, 6)
     U = inputs.random_config(dims, 35)
     ref = None
     for block, grid, remap, nl in ((256, 0, 1, 1), (64, 0, 0, 2), (128, 16, 1, 4), (192, 8, 0, 1),
-                                   (64, 24, 1, 4), (256, 0, 0, 2), (128, 0, 2, 1), (64, 16, 2, 2)):
+                                   (64, 24, 1, 4), (256, 0, 0, 2), (128, 0, 2, 1), (64, 16, 2, 2),
+                                   (64, 0, 3, 1), (128, 16, 3, 2)):
         lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F64)
         su2.su2_set_launch(lat.h, block, grid, remap, nl)
         lat.set_links(U)
@@ -200,7 +201,7 @@ def test_launch_shapes_bitwise_fp32(su2):
     dims = (8, 6, 4, 10)
     U = inputs.random_config(dims, 37).astype(np.float32).astype(np.float64)
     out = []
-    for launch in ((256, 0, 1, 1), (128, 0, 1, 2), (64, 16, 0, 4), (192, 8, 1, 2), (128, 0, 2, 1)):
+    for launch in ((256, 0, 1, 1), (128, 0, 1, 2), (64, 16, 0, 4), (192, 8, 1, 2), (128, 0, 2, 1), (64, 0, 3, 1)):
         lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F32)
         su2.su2_set_launch(lat.h, *launch)
         assert su2.su2_get_launch(lat.h) == launch
@@ -290,7 +291,7 @@ def test_errors(su2):
         lat.wilson_loops(5, 2)
     with pytest.raises(su2.SU2Error):
         su2.su2_set_launch(lat.h, 100, 0, 1)
-    for bad in ((128, 0, 3, 1), (128, 0, -1, 1), (128, 12, 1, 1), (128, 0, 1, 3)):
+    for bad in ((128, 0, 4, 1), (128, 0, -1, 1), (128, 12, 1, 1), (128, 0, 1, 3)):
         with pytest.raises(su2.SU2Error) as e:
             su2.su2_set_launch(lat.h, *bad)
         assert e.value.status == su2.EINVAL, bad

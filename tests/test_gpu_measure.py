@@ -60,7 +60,7 @@ def test_ape_and_wilson(su2, orc, dims):
         lat.close()
 
 
-@pytest.mark.parametrize("launch", [(64, 0, 1, 2), (128, 16, 0, 4), (192, 8, 1, 1), (256, 0, 1, 1)])
+@pytest.mark.parametrize("launch", [(64, 0, 1, 2), (128, 16, 0, 4), (192, 8, 1, 1), (256, 0, 1, 1), (64, 0, 3, 1)])
 def test_measurements_any_launch_shape(su2, orc, launch):
     """Plaquette, Polyakov loop, APE smearing and Wilson loops agree with the
     oracle under every launch shape (block size = tile size of the
