@@ -166,6 +166,13 @@ su2_status su2_ape_smear(su2_lattice lat, double alpha, int nsteps);
  * Synchronises. */
 su2_status su2_wilson_loops(su2_lattice lat, int Rmax, int Tmax, double *out);
 
+/* Free the measurement buffers the handle keeps between calls: the smeared
+ * links (2 x 3V links), the Wilson-line buffer (3 Rmax V quaternions: 382 MB
+ * for Rmax = 12 at 24^3 x 48 in binary32) and the Wilson-loop partials.  The
+ * next su2_ape_smear / su2_wilson_loops allocates them again; the smeared
+ * links are gone (su2_get_smeared: ESTATE).  Synchronises. */
+su2_status su2_release_buffers(su2_lattice lat);
+
 /* Copy links to / from a host array in the canonical layout (V*16 float64).
  * set rounds to binary32 for SU2_F32 lattices and rejects non-finite values
  * or links with |1 - |U|^2| > 1e-6 (EINVAL). */

@@ -1457,6 +1457,20 @@ su2_status su2_wilson_loops(su2_lattice E, int Rmax, int Tmax, double *out) {
     return finish(E);
 }
 
+su2_status su2_release_buffers(su2_lattice E) {
+    CHK(enter(E));
+    HIPCHK(hipStreamSynchronize(E->stream()));
+    for (void **b : {&E->sm[0], &E->sm[1], &E->wl_s}) {
+        if (*b) HIPCHK(hipFree(*b));
+        *b = nullptr;
+    }
+    if (E->wpart) HIPCHK(hipFree(E->wpart));
+    E->wpart = nullptr;
+    E->wl_s_bytes = E->wpart_bytes = 0;
+    E->sm_cur = -1;
+    return SU2_OK;
+}
+
 su2_status su2_get_links(su2_lattice E, double *host) {
     CHK(enter(E));
     if (!host) return SU2_EINVAL;

@@ -59,6 +59,7 @@ _SIGS = {
     "su2_polyakov": (_I, [_P, _P]),
     "su2_ape_smear": (_I, [_P, _D, _I]),
     "su2_wilson_loops": (_I, [_P, _I, _I, _P]),
+    "su2_release_buffers": (_I, [_P]),
     "su2_get_links": (_I, [_P, _P]),
     "su2_set_links": (_I, [_P, _P]),
     "su2_get_smeared": (_I, [_P, _P]),
@@ -188,6 +189,10 @@ def su2_wilson_loops(h, rmax, tmax):
     out = np.zeros((rmax, tmax))
     _chk(_lib.su2_wilson_loops(h, rmax, tmax, _ptr(out)), "su2_wilson_loops")
     return out
+
+
+def su2_release_buffers(h):
+    _chk(_lib.su2_release_buffers(h), "su2_release_buffers")
 
 
 def su2_get_links(h, volume=None):

@@ -57,6 +57,15 @@ def test_ape_and_wilson(su2, orc, dims):
         lat.heatbath(2.5, 1, 1)
         with pytest.raises(su2.SU2Error):
             lat.get_smeared()
+        # released measurement buffers come back on demand
+        lat.ape_smear(0.7, 5)
+        su2.su2_release_buffers(lat.h)
+        with pytest.raises(su2.SU2Error) as e:
+            lat.get_smeared()
+        assert e.value.status == su2.ESTATE
+        U1 = lat.get_links()
+        W = lat.wilson_loops(Rm, Tm)
+        assert np.abs(W - orc.wilson(dims, U1, Rm, Tm)).max() < tw
         lat.close()
 
 
