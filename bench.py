@@ -433,7 +433,7 @@ def main():
                     help="host threads for the all-core oracle figure (0: min(16, cores))")
     ap.add_argument("--launch", default=None,
                     help="block,grid,xcd_remap,links_per_lane (skips tuning)")
-    ap.add_argument("--reps", type=int, default=7,
+    ap.add_argument("--reps", type=int, default=11,
                     help="timed repetitions of K steps; value is the median repetition")
     ap.add_argument("--no-control", action="store_true", help="skip the 64^4 control in the c2 line")
     args = ap.parse_args()
