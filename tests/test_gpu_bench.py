@@ -35,6 +35,8 @@ def test_bench_json_contract():
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["sample"]
     assert rf["avg_launch_source"] and 0 < rf["step_frac"] < 1 and rf["links_in_infinity_cache"] is True
+    ko = rf["kernel_only"]
+    assert 0 < ko["avg_launch_us"] and abs(ko["frac"] - rf["bytes_per_launch"] / ko["avg_launch_us"] / 8e6) < 1e-9
     assert len(d["timing"]["rep_ms_per_step"]) == 11
     assert d["overrelax"]["frac"] > 0 and d["fp64_plain"]["default"]["value"] > 0
     c = d["control64"]
