@@ -775,8 +775,11 @@ __global__ void k_err_to_host(const DevState *st, unsigned *out) { *out = st->er
 // U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag and the backward staple
 // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)] with a binary64 norm.
 // src_raw: read the lattice links (first step) or the smeared buffer.
-// Grid row blockIdx.y = parity; a lane updates the three spatial links of
-// its site.
+// Work item v = 2 tile + parity: the two parities of a tile are neighbours
+// in the walk, so an XCD updates both halves of its share of the lattice
+// while the links they share are in its L2 (with the parities in separate
+// passes every link was fetched twice).  A lane updates the three spatial
+// links of its site.
 
 // APE step of the three spatial links of one site (paper Sec. 2, APE
 // equation).  Their twelve staples touch 24 distinct links: the three own
@@ -846,9 +849,9 @@ __device__ __forceinline__ void ape_site(const LatDesc &d, const Blocks<T, 3> &B
 
 template <class T>
 __global__ __launch_bounds__(256) void k_ape(KArgs a, const void *src, int src_raw, void *dst, T alpha) {
-    const int par = (int)blockIdx.y;
-    for_each_tile(a.ntiles, a.xcd_remap, [&](int tile) {
-        const Tile tl = load_tile(a.tiles, tile);
+    for_each_tile(2 * a.ntiles, a.xcd_remap, [&](int v) {
+        const Tile tl = load_tile(a.tiles, v >> 1);
+        const int par = v & 1;
         const LatDesc d = load_desc(a.desc + tl.x);
         const Blocks<T, 3> Bs = blocks<T, 3>(src, src_raw ? d.off : d.soff, d.vh);
         const Blocks<T, 3> Bd = blocks<T, 3>(dst, d.soff, d.vh);
@@ -966,17 +969,26 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, int
             }
         }
     }
-    DD acc[TMAX];
+    // Wavefront sums by binary64 butterflies in a fixed order (each lane holds
+    // a plain binary64 sum; a compensated butterfly cost as much as a tenth of
+    // the kernel's instructions), then the workgroup's wavefronts combined by
+    // compensated sums in thread 0.
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
 #pragma unroll
-    for (int k = 0; k < TMAX; ++k) acc[k] = DD{sum[k], 0.0};
-    dd_block_sum<TMAX>(acc, lds);
+    for (int k = 0; k < TMAX; ++k) {
+        const double ws = wave_sum_f64(sum[k]);
+        if (lane == 0) lds[wave * TMAX + k] = DD{ws, 0.0};
+    }
+    __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < TMAX; ++k)
             if (k < Tmax) {
+                DD acc = lds[k];
+                for (int w = 1; w < nw; ++w) acc = dd_add(acc, lds[w * TMAX + k]);
                 double *p = part + 2 * (((long long)(R - 1) * gridDim.x + blockIdx.x) * Tmax + k);
-                p[0] = acc[k].hi;
-                p[1] = acc[k].lo;
+                p[0] = acc.hi;
+                p[1] = acc.lo;
             }
 }
 
@@ -1149,7 +1161,9 @@ void launch_err_to_host(const DevState *st, unsigned *out, hipStream_t s) {
 
 void launch_ape(const KArgs &a, bool f32, const void *src, int src_raw, void *dst, double alpha, int block,
                 int grid, hipStream_t s) {
-    const dim3 g(grid_of(a, grid).x, 2);  // y: parity
+    KArgs w = a;
+    w.ntiles = 2 * a.ntiles;  // work items (tile, parity)
+    const dim3 g = grid_of(w, grid);
     if (f32) hipLaunchKernelGGL((k_ape<float>), g, dim3(block), 0, s, a, src, src_raw, dst, (float)alpha);
     else hipLaunchKernelGGL((k_ape<double>), g, dim3(block), 0, s, a, src, src_raw, dst, alpha);
 }
