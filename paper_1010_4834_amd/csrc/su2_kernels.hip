@@ -913,8 +913,8 @@ __global__ __launch_bounds__(256) void k_wlines(KArgs a, const void *sp, int sp_
 // assignment), each lane summing in binary64, then one compensated block sum
 // per (R, workgroup, T).
 template <class T, int TMAX, int NC>
-__global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, int ncols, int nctiles,
-                                                const Q<T> *sl, double *part) {
+__device__ __forceinline__ void wtrace_body(const KArgs &a, int Rmax, int Tmax, int ncols, int nctiles,
+                                            const Q<T> *sl, double *part) {
     __shared__ DD lds[TMAX * 4];
     const int R = blockIdx.y + 1;
     double sum[TMAX];
@@ -990,6 +990,22 @@ __global__ __launch_bounds__(256) void k_wtrace(KArgs a, int Rmax, int Tmax, int
                 p[0] = acc.hi;
                 p[1] = acc.lo;
             }
+}
+
+// Binary32 traces are held to 128 registers (4 waves per SIMD): under that
+// bound the compiler also schedules the unrolled offsets without copying the
+// binary64 sums around their run-time bounds, 10% faster at 24^3 x 48 than
+// the same code unbounded (122 registers, also 4 waves).  Binary64 traces
+// need more registers and run unbounded (the bound would spill).
+template <int TMAX, int NC>
+__global__ __launch_bounds__(256, 4) void k_wtrace(KArgs a, int Rmax, int Tmax, int ncols, int nctiles,
+                                                   const Q<float> *sl, double *part) {
+    wtrace_body<float, TMAX, NC>(a, Rmax, Tmax, ncols, nctiles, sl, part);
+}
+template <int TMAX, int NC>
+__global__ __launch_bounds__(256) void k_wtrace64(KArgs a, int Rmax, int Tmax, int ncols, int nctiles,
+                                                  const Q<double> *sl, double *part) {
+    wtrace_body<double, TMAX, NC>(a, Rmax, Tmax, ncols, nctiles, sl, part);
 }
 
 // One block per (R, T): fixed-order sum over the k_wtrace workgroups'
@@ -1199,10 +1215,17 @@ static void launch_wtrace_nc(const KArgs &a, int Rmax, int Tmax, long long V, co
     const dim3 g(wtrace_groups(a), (unsigned)Rmax), b((unsigned)block);
     const int ncols = (int)(V / NC), nct = (ncols + block - 1) / block;
     const Q<T> *l = (const Q<T> *)sl;
-    if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<T, 4, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
-    else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<T, 8, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
-    else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<T, 16, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
-    else if constexpr (NC == 2) hipLaunchKernelGGL((k_wtrace<T, 32, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+    if constexpr (sizeof(T) == 4) {
+        if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace<4, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+        else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace<8, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+        else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace<16, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+        else if constexpr (NC == 2) hipLaunchKernelGGL((k_wtrace<32, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+    } else {
+        if (Tmax <= 4) hipLaunchKernelGGL((k_wtrace64<4, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+        else if (Tmax <= 8) hipLaunchKernelGGL((k_wtrace64<8, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+        else if (Tmax <= 16) hipLaunchKernelGGL((k_wtrace64<16, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+        else if constexpr (NC == 2) hipLaunchKernelGGL((k_wtrace64<32, NC>), g, b, 0, s, a, Rmax, Tmax, ncols, nct, l, part);
+    }
 }
 
 template <class T>
