@@ -53,6 +53,15 @@ HB_TRAFFIC = {"sources_sha256": "07caf04a1abdd3a90bce1b9f8d531e9e8f8f6deaae8eab4
 KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp", "su2_api.hip")
 
 
+def effective_grid(grid, tiles):
+    """Workgroups of a heat-bath launch that take tiles: grid 0 is one
+    workgroup per tile (the tile count rounded up to a multiple of 8); a
+    persistent grid beyond that count leaves the extra workgroups idle and
+    hands out the tiles exactly as the rounded count does."""
+    full = max(8, -(-tiles // 8) * 8)
+    return full if grid <= 0 else min(grid, full)
+
+
 def kernel_sources_sha256():
     """SHA-256 of the kernel sources, or None where they are not shipped."""
     import hashlib
@@ -409,8 +418,7 @@ def control64(su2, torch, stream, launch, seed, args):
     hb_us = 1e3 * gms / (8 * k)     # timed region, as the 32^4 roofline
     ach = hb_bytes / (hb_us * 1e-6) / 1e9
     traffic = None
-    tiles = -(-(V // 2) // (launch[0] * launch[3]))
-    eff = (launch[0], launch[1] if launch[1] > 0 else max(8, -(-tiles // 8) * 8), launch[2], launch[3])
+    eff = (launch[0], effective_grid(launch[1], -(-(V // 2) // (launch[0] * launch[3]))), launch[2], launch[3])
     if kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]:
         traffic = HB_TRAFFIC["control64"].get(eff)
     return {"workload": "64^4, beta=2.6, hot start, binary32, 1 sweep + plaquette per step",
@@ -491,9 +499,7 @@ def main():
     ev = eager_event_pass(su2, ens, n, args.steps, seed, cfg["poly"])
     hb_avg_us = 1e3 * gpu_ms / (8 * args.steps)
     traffic = None
-    # grid 0 = one workgroup per tile: the tile count rounded up to a multiple of 8
-    tiles = -(-(updates_per_step // 8) // (block * nl))
-    eff_grid = grid if grid > 0 else max(8, -(-tiles // 8) * 8)
+    eff_grid = effective_grid(grid, -(-(updates_per_step // 8) // (block * nl)))
     if args.config == "c2" and kernel_sources_sha256() == HB_TRAFFIC["sources_sha256"]:
         traffic = HB_TRAFFIC["by_launch"].get((block, eff_grid, remap, nl))
     link_b = 16

@@ -50,3 +50,18 @@ def test_every_global_name_is_defined():
             walk(child)
     walk(top)
     assert not missing, missing
+
+
+def test_traffic_lookup_grid():
+    """The stored fabric traffic is keyed by the workgroups that take tiles:
+    grid 0 and persistent grids at or beyond the (rounded) tile count hand
+    out the same tiles to the same XCDs."""
+    sys.path.insert(0, ROOT)
+    import bench
+    tiles = (32 ** 4 // 2) // 256                       # 32^4, block 256, one link per lane
+    assert bench.effective_grid(0, tiles) == bench.effective_grid(4096, tiles) == 2048
+    assert bench.effective_grid(1024, tiles) == 1024    # several tiles per workgroup: its own key
+    assert bench.effective_grid(0, 5) == 8
+    for key in bench.HB_TRAFFIC["by_launch"]:
+        block, grid, _, nl = key
+        assert bench.effective_grid(grid, (32 ** 4 // 2) // (block * nl)) == grid
