@@ -47,7 +47,11 @@ INFINITY_CACHE_BYTES = 256 << 20
 # code that orders their tiles).
 HB_TRAFFIC = {"sources_sha256": "07caf04a1abdd3a90bce1b9f8d531e9e8f8f6deaae8eab454e71226b3c40a940",
               "by_launch": {(128, 4096, 3, 1): 74254893, (64, 8192, 3, 1): 74271270,
-                            (256, 2048, 3, 1): 74096792, (64, 8192, 1, 1): 78201725},
+                            (256, 2048, 3, 1): 74096792, (64, 8192, 1, 1): 78201725,
+                            (64, 4096, 3, 1): 74274469, (128, 2048, 3, 1): 74264928,
+                            (256, 1024, 3, 1): 74101492, (64, 7168, 3, 1): 76567586,
+                            (128, 3584, 3, 1): 77331762, (256, 1792, 3, 1): 76161691,
+                            (64, 4096, 3, 2): 75745651, (128, 2048, 3, 2): 75576930},
               # the 64^4 control: 1 GiB algorithmic per launch
               "control64": {(256, 32768, 0, 1): 1267339493}}
 KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp", "su2_api.hip")
