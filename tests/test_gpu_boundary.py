@@ -120,3 +120,67 @@ def test_configuration_files(su2, orc, tmp_path):
     with pytest.raises(su2.SU2Error) as e:
         su2.su2_load(str(p))
     assert e.value.status == su2.EIO
+
+
+@pytest.mark.parametrize("prec", ["F32", "F64"])
+def test_maximum_volume_top_of_the_offset_range(su2, orc, prec):
+    """A lattice at the volume cap (2^29 sites in binary32, 2^28 in
+    binary64: 32 GiB of links either way), where a link's byte offset inside
+    its (mu, parity) block reaches 2^32 - 16.  From a cold start every
+    staple is exactly 6 x 1, so after one substep of the last block in
+    memory (mu = 3, odd sites) each link is the normalised draw of the
+    oracle's single-link sampler with alpha = 6 beta and that link's
+    counter.  Sampled links (the first, the last 24, 32 random) are read
+    from device memory and compared; the other blocks stay cold."""
+    import torch
+    P = getattr(su2, prec)
+    dims = (64, 128, 128, 512) if prec == "F32" else (64, 128, 128, 256)
+    V = int(np.prod(dims))
+    vh = V // 2
+    assert V == (1 << 29 if prec == "F32" else 1 << 28)
+    beta, seed, mu, par = 2.3, 17, 3, 1
+    print(f"maximum volume {prec}: dims {dims}, {su2.su2_link_bytes(*dims, P) >> 30} GiB of links", flush=True)
+    lat = su2.Lattice(dims, start=su2.COLD, prec=P)
+    try:
+        lat.substep(beta, seed, mu, par)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(5)
+        cbs = np.unique(np.concatenate([[0, 1, 2, 3], np.arange(vh - 24, vh), rng.integers(0, vh, 32)]))
+        blk = 2 * mu + par
+        if prec == "F32":
+            f = lat._buf.view(torch.float32)
+            idx = torch.as_tensor((blk * vh + cbs)[:, None] * 4 + np.arange(4), device="cuda")
+            got = f[idx].double().cpu().numpy()
+            # a0 of the first link of block (0, even) and of the last link of block (0, odd)
+            cold = f[torch.as_tensor(np.array([0, 4 * (2 * vh - 1)]), device="cuda")].cpu().numpy()
+        else:
+            f = lat._buf.view(torch.float64)
+            base = blk * vh * 4
+            lo = base + 2 * cbs[:, None] + np.arange(2)
+            hi = base + 2 * vh + 2 * cbs[:, None] + np.arange(2)
+            idx = torch.as_tensor(np.concatenate([lo, hi], axis=1), device="cuda")
+            got = f[idx].cpu().numpy()
+            # a0 (low plane) of the first link of block (0, even) and of the last link of block (0, odd)
+            cold = f[torch.as_tensor(np.array([0, 4 * vh + 2 * (vh - 1)]), device="cuda")].cpu().numpy()
+        assert np.all(cold == 1.0), cold
+        tag = (0 << 8) | (0 << 4) | (mu << 1) | par       # lattice 0, heat bath, (mu, parity)
+        nx = dims[0]
+        err = []
+        for k, cb in enumerate(cbs):
+            row = (2 * int(cb)) // nx
+            y, z, t = row % dims[1], (row // dims[1]) % dims[2], row // (dims[1] * dims[2])
+            s = 2 * int(cb) + ((par + y + z + t) & 1)
+            X, _ = orc.sample_link(6.0 * beta, orc.HYBRID, seed, [s, 0, tag], ubits=23 if prec == "F32" else 32)
+            err.append(float(np.abs(got[k] - X / np.linalg.norm(X)).max()))
+        err = np.array(err)
+        tol = 1e-5 if prec == "F32" else 1e-12
+        top = int(cbs.max()) * 16 + (0 if prec == "F32" else vh * 16)   # binary64: the high plane's offset
+        print(f"  {len(cbs)} sampled links up to cb {int(cbs.max())} (lane byte offset {top}): "
+              f"max |dU| {err.max():.2e}, {int((err > tol).sum())} beyond {tol:g}", flush=True)
+        assert (err > tol).sum() <= (1 if prec == "F32" else 0), err
+        # unit links, and no link of the updated block left cold
+        assert np.all(np.abs(np.linalg.norm(got, axis=1) - 1) < 1e-6) and np.all(got[:, 0] < 1.0)
+    finally:
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
