@@ -43,6 +43,9 @@ def test_host_validation():
     with pytest.raises(su2.SU2Error) as e:
         su2.su2_ensemble_create([(8, 8, 8, 8)], [-1.0], su2.HOT, 1, su2.F32)
     assert e.value.status == su2.EINVAL
+    with pytest.raises(su2.SU2Error) as e:           # an empty ensemble
+        su2.su2_ensemble_create(np.zeros((0, 4), dtype=np.int32), [], su2.HOT, 1, su2.F32)
+    assert e.value.status == su2.EINVAL
     assert su2._lib.su2_status_str(-7).decode().startswith("non-finite")
 
 

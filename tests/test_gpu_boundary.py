@@ -184,3 +184,24 @@ def test_maximum_volume_top_of_the_offset_range(su2, orc, prec):
         lat.close()
         del lat
         torch.cuda.empty_cache()
+
+
+def test_zero_sweeps_change_nothing(su2):
+    """Empty work: zero heat-bath or over-relaxation sweeps and an ensemble
+    run of zero sweeps leave links, sweep counter and try counts as they
+    were, and return empty series."""
+    lat = su2.Lattice((4, 4, 4, 6), start=su2.HOT, seed=3, prec=su2.F32)
+    U = lat.get_links()
+    lat.heatbath(2.3, 0, 3)
+    lat.overrelax(0)
+    assert lat.sweep == 0 and np.array_equal(lat.get_links(), U)
+    lat.close()
+    ens = su2.Ensemble([(4, 4, 4, 4), (6, 4, 4, 2)], [2.0, 2.4], start=su2.HOT, seed=4, prec=su2.F64)
+    links = [ens.get_links(i) for i in range(2)]
+    P, L = ens.run(0, 4)
+    assert P.shape == (2, 0) and L.shape == (2, 0)
+    P, L = ens.run(3, 4, measure_every=5)          # fewer sweeps than one measurement unit
+    assert P.shape == (2, 0) and L.shape == (2, 0)
+    assert not np.array_equal(ens.get_links(0), links[0])   # the three sweeps did run
+    ens.close()
+
