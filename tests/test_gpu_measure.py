@@ -95,6 +95,8 @@ def test_measurements_any_launch_shape(su2, orc, launch):
     ((2, 2, 4, 8), 2, 8),     # T = Nt: the temporal transport wraps the full period
     ((2, 4, 2, 12), 2, 12),   # column height 6 in binary32 (Nt divisible by 6)
     ((2, 2, 2, 16), 2, 12),   # column height 4 in binary32 (Nt divisible by 4, not 6)
+    ((2, 2, 2, 4), 2, 3),     # the smallest time bound (T <= 4), below it; column height 4
+    ((2, 4, 2, 6), 2, 4),     # the smallest time bound, at it; column height 6
 ])
 def test_wilson_columns_and_long_times(su2, orc, dims, Rm, Tm):
     """The trace kernel takes columns of sites along t and transports the
