@@ -113,6 +113,9 @@ struct su2_ensemble_s {
     // captured sweep graphs by (measurement mask, sweeps per measurement,
     // measured units per graph)
     std::map<unsigned long long, hipGraphExec_t> graphs;
+    // whole runs captured as one graph (sweeps, series reduction, error
+    // word) by (measurement mask, sweeps per measurement, sweeps)
+    std::map<unsigned long long, hipGraphExec_t> run_graphs;
 
     void *sm[2] = {nullptr, nullptr};
     int sm_cur = -1;  // index of the valid smeared buffer, -1 none
@@ -279,10 +282,17 @@ const Tile *hb_tiles(const su2_ensemble_s *E, int mu) {
     return (mu == 3 || E->remap == 2) ? E->mtiles_z : E->mtiles;
 }
 
+void drop_run_graphs(su2_ensemble_s *E) {
+    for (auto &g : E->run_graphs)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
+    E->run_graphs.clear();
+}
+
 void drop_graphs(su2_ensemble_s *E) {
     for (auto &g : E->graphs)
         if (g.second) (void)hipGraphExecDestroy(g.second);
     E->graphs.clear();
+    drop_run_graphs(E);
 }
 
 // ---- per-kernel event timing -------------------------------------------
@@ -481,8 +491,8 @@ su2_status upload_state(su2_ensemble_s *E) {
 // stream, after which the error word (non-finite staples, sampler try-cap
 // hits since the last report) is read.  A non-zero word is this call's
 // ENUMERIC and is cleared, so the next call starts clean.
-su2_status finish(su2_ensemble_s *E) {
-    su2::launch_err_to_host(E->st, E->derr, E->stream());
+su2_status finish(su2_ensemble_s *E, bool err_enqueued = false) {
+    if (!err_enqueued) su2::launch_err_to_host(E->st, E->derr, E->stream());
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(E->stream()));
     if (*E->herr == 0u) return SU2_OK;
@@ -698,12 +708,65 @@ su2_status run_units(su2_ensemble_s *E, int nunits, int meas, int every) {
     return SU2_OK;
 }
 
+// A whole run as one graph: its measured units, the series reduction of its
+// one batch, the unmeasured remainder and the copy of the error word.  One
+// launch instead of one per graph size (each hand-over between graphs left
+// the GPU idle for ~8 us) and the series kernels right behind the last
+// sweep; kept for runs of up to RUN_GRAPH_MAX_SWEEPS sweeps, at most
+// RUN_GRAPH_MAX of them per handle.
+constexpr int RUN_GRAPH_MAX_SWEEPS = 256;
+constexpr size_t RUN_GRAPH_MAX = 8;
+
+bool run_graph_ok(const su2_ensemble_s *E, int nsweeps, int nm) {
+    return !E->timing && nsweeps > 1 && nsweeps <= RUN_GRAPH_MAX_SWEEPS && nm <= E->nslots &&
+           !std::getenv("SU2_NO_GRAPH");
+}
+
+su2_status capture_run(su2_ensemble_s *E, int meas, int every, int nsweeps, hipGraphExec_t *out) {
+    const int nm = meas ? nsweeps / every : 0;
+    HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
+    su2_status st = SU2_OK;
+    for (int k = 0; k < nm && st == SU2_OK; ++k) st = enqueue_unit(E, meas, every, E->own);
+    if (st == SU2_OK && nm > 0) st = series_batch(E, meas, 0, nm, E->own);
+    for (int k = nm * every; k < nsweeps && st == SU2_OK; ++k) st = enqueue_unit(E, 0, 1, E->own);
+    if (st == SU2_OK) su2::launch_err_to_host(E->st, E->derr, E->own);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(E->own, &g);
+    if (st != SU2_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    HIPCHK(e);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    return SU2_OK;
+}
+
 // nsweeps sweeps; with meas, sweep k (0-based) of the run is measured when
 // (k + 1) % every == 0 (nsweeps / every measurements, series batches of at
 // most nslots of them) and the remaining nsweeps % every sweeps at the end
-// measure nothing.
-su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every) {
+// measure nothing.  With err_enqueued the run may also enqueue the copy of
+// the error word (then *err_enqueued is set and finish() skips it).
+su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every, bool *err_enqueued = nullptr) {
     const int nm = meas ? nsweeps / every : 0;
+    if (err_enqueued) *err_enqueued = false;
+    if (err_enqueued && run_graph_ok(E, nsweeps, nm)) {
+        const unsigned long long key = graph_key(meas, every, nsweeps);
+        auto it = E->run_graphs.find(key);
+        if (it == E->run_graphs.end()) {
+            if (E->run_graphs.size() >= RUN_GRAPH_MAX) drop_run_graphs(E);
+            hipGraphExec_t g = nullptr;
+            CHK(capture_run(E, meas, every, nsweeps, &g));
+            it = E->run_graphs.emplace(key, g).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second, E->stream()));
+        *err_enqueued = true;
+        E->hst.sweep += (unsigned)nsweeps;
+        E->updates += (unsigned long long)nsweeps * (unsigned long long)E->total_links;
+        invalidate_measure_buffers(E);
+        return SU2_OK;
+    }
     for (int done = 0; done < nm; done += E->nslots) {
         const int b = std::min(E->nslots, nm - done);
         CHK(run_units(E, b, meas, every));
@@ -722,6 +785,7 @@ su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every) {
 su2_status ensure_series(su2_ensemble_s *E, int nm) {
     const size_t need = 2 * (size_t)nm * E->n;
     if (need > E->hser_cap) {
+        drop_run_graphs(E);  // they hold the old series pointers
         if (E->hser) (void)hipHostFree(E->hser);
         E->hser = E->dser = nullptr;
         E->hser_cap = 0;
@@ -1186,10 +1250,9 @@ su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, int measure_every, uint
     E->run_plaq = E->dser;
     E->run_poly = E->dser + (size_t)nm * E->n;
     E->run_nm = nm;
-    CHK(run_sweeps(E, nsweeps, nm > 0 ? meas : 0, measure_every));
-    hipStream_t s = E->stream();
-    (void)s;
-    const su2_status st = finish(E);
+    bool err_enqueued = false;
+    CHK(run_sweeps(E, nsweeps, nm > 0 ? meas : 0, measure_every, &err_enqueued));
+    const su2_status st = finish(E, err_enqueued);
     if (st == SU2_EDEVICE) return st;
     for (int m = 0; m < 2 && nm > 0; ++m) {
         double *dst = m == 0 ? plaq : poly;
@@ -1337,8 +1400,9 @@ su2_status su2_heatbath(su2_lattice E, double beta, int nsweeps, uint64_t seed) 
     if (nsweeps == 0) return SU2_OK;
     CHK(set_beta(E, beta));
     CHK(set_seed(E, seed));
-    CHK(run_sweeps(E, nsweeps, 0, 1));
-    return finish(E);
+    bool err_enqueued = false;
+    CHK(run_sweeps(E, nsweeps, 0, 1, &err_enqueued));
+    return finish(E, err_enqueued);
 }
 
 su2_status su2_heatbath_substep(su2_lattice E, double beta, uint64_t seed, int mu, int parity) {
