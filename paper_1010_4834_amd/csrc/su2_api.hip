@@ -107,6 +107,9 @@ struct su2_ensemble_s {
     size_t hser_cap = 0;            // doubles
     double *run_plaq = nullptr, *run_poly = nullptr;  // device targets of the current run
     int run_nm = 0;
+    // mapped host words: [0] the error word written by the device, [4..7]
+    // the run state (seed low and high, sweep, run base) written by the host
+    // for the first node of a captured run
     unsigned *herr = nullptr, *derr = nullptr;
 
     hipStream_t own = nullptr, user = nullptr;
@@ -708,10 +711,12 @@ su2_status run_units(su2_ensemble_s *E, int nunits, int meas, int every) {
     return SU2_OK;
 }
 
-// A whole run as one graph: its measured units, the series reduction of its
-// one batch, the unmeasured remainder and the copy of the error word.  One
-// launch instead of one per graph size (each hand-over between graphs left
-// the GPU idle for ~8 us) and the series kernels right behind the last
+// A whole run as one graph: the device state from the run state in mapped
+// host memory, its measured units, the series reduction of its one batch,
+// the unmeasured remainder and the copy of the error word.  One launch
+// instead of a state kernel and one launch per graph size (the GPU idled
+// ~9 us between the state kernel and the first sweep, and ~8 us at each
+// hand-over between graphs), and the series kernels right behind the last
 // sweep; kept for runs of up to RUN_GRAPH_MAX_SWEEPS sweeps, at most
 // RUN_GRAPH_MAX of them per handle.
 constexpr int RUN_GRAPH_MAX_SWEEPS = 256;
@@ -726,6 +731,7 @@ su2_status capture_run(su2_ensemble_s *E, int meas, int every, int nsweeps, hipG
     const int nm = meas ? nsweeps / every : 0;
     HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
     su2_status st = SU2_OK;
+    su2::launch_set_state_mapped(E->st, E->derr + 4, E->own);
     for (int k = 0; k < nm && st == SU2_OK; ++k) st = enqueue_unit(E, meas, every, E->own);
     if (st == SU2_OK && nm > 0) st = series_batch(E, meas, 0, nm, E->own);
     for (int k = nm * every; k < nsweeps && st == SU2_OK; ++k) st = enqueue_unit(E, 0, 1, E->own);
@@ -746,12 +752,23 @@ su2_status capture_run(su2_ensemble_s *E, int meas, int every, int nsweeps, hipG
 // nsweeps sweeps; with meas, sweep k (0-based) of the run is measured when
 // (k + 1) % every == 0 (nsweeps / every measurements, series batches of at
 // most nslots of them) and the remaining nsweeps % every sweeps at the end
-// measure nothing.  With err_enqueued the run may also enqueue the copy of
-// the error word (then *err_enqueued is set and finish() skips it).
-su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every, bool *err_enqueued = nullptr) {
+// measure nothing.  With err_enqueued the run may be one captured graph,
+// which also sets the device state from the host mirror and copies the error
+// word (then *err_enqueued is set and finish() skips the copy); otherwise,
+// with upload, the state is set by upload_state first.
+su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every, bool *err_enqueued = nullptr,
+                      bool upload = false) {
     const int nm = meas ? nsweeps / every : 0;
     if (err_enqueued) *err_enqueued = false;
     if (err_enqueued && run_graph_ok(E, nsweeps, nm)) {
+        // every call synchronises before it returns, so no replay of a run
+        // graph is pending while these words are rewritten
+        E->hst.next = E->hst.sweep;
+        volatile unsigned *rs = E->herr + 4;
+        rs[0] = (unsigned)E->hst.seed;
+        rs[1] = (unsigned)(E->hst.seed >> 32);
+        rs[2] = E->hst.sweep;
+        rs[3] = E->hst.run_base;
         const unsigned long long key = graph_key(meas, every, nsweeps);
         auto it = E->run_graphs.find(key);
         if (it == E->run_graphs.end()) {
@@ -767,6 +784,7 @@ su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every, bool 
         invalidate_measure_buffers(E);
         return SU2_OK;
     }
+    if (upload) CHK(upload_state(E));
     for (int done = 0; done < nm; done += E->nslots) {
         const int b = std::min(E->nslots, nm - done);
         CHK(run_units(E, b, meas, every));
@@ -1245,13 +1263,12 @@ su2_status su2_ensemble_run(su2_ensemble E, int nsweeps, int measure_every, uint
     if (nm > 0) CHK(ensure_series(E, nm));
     E->hst.seed = seed;
     E->hst.run_base = E->hst.sweep;
-    CHK(upload_state(E));
     // the series kernels write measurement k of lattice l to [l * nm + k]
     E->run_plaq = E->dser;
     E->run_poly = E->dser + (size_t)nm * E->n;
     E->run_nm = nm;
     bool err_enqueued = false;
-    CHK(run_sweeps(E, nsweeps, nm > 0 ? meas : 0, measure_every, &err_enqueued));
+    CHK(run_sweeps(E, nsweeps, nm > 0 ? meas : 0, measure_every, &err_enqueued, true));
     const su2_status st = finish(E, err_enqueued);
     if (st == SU2_EDEVICE) return st;
     for (int m = 0; m < 2 && nm > 0; ++m) {

@@ -68,6 +68,7 @@ void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp
 // state, set by a one-thread kernel so that no host synchronisation is
 // needed before the work that reads them (the error word is left alone).
 void launch_set_state(DevState *st, unsigned long long seed, unsigned sweep, unsigned run_base, hipStream_t s);
+void launch_set_state_mapped(DevState *st, const unsigned *src, hipStream_t s);
 // Zero the error word.
 void launch_clear_err(DevState *st, hipStream_t s);
 // Copy the error word to `out` (mapped host memory).

@@ -764,6 +764,16 @@ __global__ void k_set_state(DevState *st, unsigned long long seed, unsigned swee
     st->run_base = run_base;
 }
 
+// The same from the run state the host wrote into mapped host memory before
+// launching a captured run (words: seed low, seed high, sweep, run base), so
+// that the run's first node needs no kernel arguments of its own.
+__global__ void k_set_state_mapped(DevState *st, const volatile unsigned *src) {
+    st->seed = (unsigned long long)src[0] | ((unsigned long long)src[1] << 32);
+    st->sweep = src[2];
+    st->next = src[2];
+    st->run_base = src[3];
+}
+
 __global__ void k_clear_err(DevState *st) { st->err = 0u; }
 
 __global__ void k_err_to_host(const DevState *st, unsigned *out) { *out = st->err; }
@@ -1166,6 +1176,10 @@ void launch_series(const LatDesc *desc, int nlat, const double *pp, long long pp
 
 void launch_set_state(DevState *st, unsigned long long seed, unsigned sweep, unsigned run_base, hipStream_t s) {
     hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st, seed, sweep, run_base);
+}
+
+void launch_set_state_mapped(DevState *st, const unsigned *src, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_state_mapped, dim3(1), dim3(1), 0, s, st, src);
 }
 
 void launch_clear_err(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(1), 0, s, st); }
