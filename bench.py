@@ -45,15 +45,15 @@ INFINITY_CACHE_BYTES = 256 << 20
 # per lane; a grid of 0 counts as its effective size, one workgroup per
 # tile).  Valid only for the sources with this hash (the kernels and the host
 # code that orders their tiles).
-HB_TRAFFIC = {"sources_sha256": "07caf04a1abdd3a90bce1b9f8d531e9e8f8f6deaae8eab454e71226b3c40a940",
-              "by_launch": {(128, 4096, 3, 1): 74254893, (64, 8192, 3, 1): 74271270,
-                            (256, 2048, 3, 1): 74096792, (64, 8192, 1, 1): 78201725,
-                            (64, 4096, 3, 1): 74274469, (128, 2048, 3, 1): 74264928,
-                            (256, 1024, 3, 1): 74101492, (64, 7168, 3, 1): 76567586,
-                            (128, 3584, 3, 1): 77331762, (256, 1792, 3, 1): 76161691,
-                            (64, 4096, 3, 2): 75745651, (128, 2048, 3, 2): 75576930},
+HB_TRAFFIC = {"sources_sha256": "0f9e12243cacaf6a7b46291161e8498bed0565d7b754d55ae6fd4918137b7fb9",
+              "by_launch": {(128, 4096, 3, 1): 74249637, (64, 8192, 3, 1): 74272729,
+                            (256, 2048, 3, 1): 74090744, (64, 8192, 1, 1): 78153193,
+                            (64, 4096, 3, 1): 74272987, (128, 2048, 3, 1): 74277195,
+                            (256, 1024, 3, 1): 74108357, (64, 7168, 3, 1): 76716103,
+                            (128, 3584, 3, 1): 77494977, (256, 1792, 3, 1): 76472175,
+                            (64, 4096, 3, 2): 75660387, (128, 2048, 3, 2): 75575508},
               # the 64^4 control: 1 GiB algorithmic per launch
-              "control64": {(256, 32768, 0, 1): 1267339493}}
+              "control64": {(256, 32768, 0, 1): 1267400492}}
 KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp", "su2_api.hip")
 
 
