@@ -296,10 +296,13 @@ su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
  * poly[i*M + k]; the last nsweeps % measure_every sweeps measure nothing.
  * Either pointer may be NULL to skip that measurement.  The sweeps (eight
  * substep launches each; the plaquette is summed inside the odd substeps of
- * measured sweeps) are replayed from captured HIP graphs of up to 16 sweeps
- * (environment SU2_GRAPH_SWEEPS) and of the smaller powers of two; partial
- * sums are reduced once per batch of measurements and the series stay on
- * the device until the end.  Measuring does not change the Markov chain.
+ * measured sweeps) are replayed from captured HIP graphs: a run of 2 to 256
+ * sweeps is one graph (run state, sweeps, series reduction and error word),
+ * captured on the first run of that length, measure_every and measurement
+ * choice; longer runs replay graphs of up to 16 sweeps (environment
+ * SU2_GRAPH_SWEEPS) and of the smaller powers of two.  Partial sums are
+ * reduced once per batch of measurements and the series stay on the device
+ * until the end.  Measuring does not change the Markov chain.
  * Synchronises once; ENUMERIC as for su2_heatbath.  measure_every >= 1,
  * nsweeps >= 0, else EINVAL.  Environment SU2_NO_GRAPH launches every
  * kernel directly. */

@@ -712,8 +712,8 @@ su2_status run_units(su2_ensemble_s *E, int nunits, int meas, int every) {
 }
 
 // A whole run as one graph: the device state from the run state in mapped
-// host memory, its measured units, the series reduction of its one batch,
-// the unmeasured remainder and the copy of the error word.  One launch
+// host memory, its measured units with the series reduction behind each
+// batch of them, the unmeasured remainder and the copy of the error word.  One launch
 // instead of a state kernel and one launch per graph size (the GPU idled
 // ~9 us between the state kernel and the first sweep, and ~8 us at each
 // hand-over between graphs), and the series kernels right behind the last
@@ -722,9 +722,8 @@ su2_status run_units(su2_ensemble_s *E, int nunits, int meas, int every) {
 constexpr int RUN_GRAPH_MAX_SWEEPS = 256;
 constexpr size_t RUN_GRAPH_MAX = 8;
 
-bool run_graph_ok(const su2_ensemble_s *E, int nsweeps, int nm) {
-    return !E->timing && nsweeps > 1 && nsweeps <= RUN_GRAPH_MAX_SWEEPS && nm <= E->nslots &&
-           !std::getenv("SU2_NO_GRAPH");
+bool run_graph_ok(const su2_ensemble_s *E, int nsweeps) {
+    return !E->timing && nsweeps > 1 && nsweeps <= RUN_GRAPH_MAX_SWEEPS && !std::getenv("SU2_NO_GRAPH");
 }
 
 su2_status capture_run(su2_ensemble_s *E, int meas, int every, int nsweeps, hipGraphExec_t *out) {
@@ -732,8 +731,11 @@ su2_status capture_run(su2_ensemble_s *E, int meas, int every, int nsweeps, hipG
     HIPCHK(hipStreamBeginCapture(E->own, hipStreamCaptureModeRelaxed));
     su2_status st = SU2_OK;
     su2::launch_set_state_mapped(E->st, E->derr + 4, E->own);
-    for (int k = 0; k < nm && st == SU2_OK; ++k) st = enqueue_unit(E, meas, every, E->own);
-    if (st == SU2_OK && nm > 0) st = series_batch(E, meas, 0, nm, E->own);
+    for (int done = 0; done < nm && st == SU2_OK; done += E->nslots) {
+        const int b = std::min(E->nslots, nm - done);
+        for (int k = 0; k < b && st == SU2_OK; ++k) st = enqueue_unit(E, meas, every, E->own);
+        if (st == SU2_OK) st = series_batch(E, meas, done, b, E->own);
+    }
     for (int k = nm * every; k < nsweeps && st == SU2_OK; ++k) st = enqueue_unit(E, 0, 1, E->own);
     if (st == SU2_OK) su2::launch_err_to_host(E->st, E->derr, E->own);
     hipGraph_t g = nullptr;
@@ -760,7 +762,7 @@ su2_status run_sweeps(su2_ensemble_s *E, int nsweeps, int meas, int every, bool 
                       bool upload = false) {
     const int nm = meas ? nsweeps / every : 0;
     if (err_enqueued) *err_enqueued = false;
-    if (err_enqueued && run_graph_ok(E, nsweeps, nm)) {
+    if (err_enqueued && run_graph_ok(E, nsweeps)) {
         // every call synchronises before it returns, so no replay of a run
         // graph is pending while these words are rewritten
         E->hst.next = E->hst.sweep;

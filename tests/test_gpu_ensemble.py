@@ -168,11 +168,10 @@ def test_measuring_does_not_change_the_chain(su2, prec):
 
 @pytest.mark.parametrize("prec", ["F64", "F32"])
 def test_multi_sweep_graphs_match_direct_launches(su2, prec):
-    """21 sweeps replay graphs of 16, 4 and 1 sweeps, 5 sweeps graphs of 4
-    and 1, and 37 sweeps measured every second sweep graphs of 8, 8 and 2
-    two-sweep units and one plain sweep; links, plaquette and Polyakov
-    series are bit for bit those of the same sweeps launched one kernel at a
-    time (SU2_NO_GRAPH)."""
+    """Runs of 21 sweeps, 5 sweeps and 37 sweeps measured every second sweep
+    (18 two-sweep units and one unmeasured sweep), each replayed as one
+    captured run graph; links, plaquette and Polyakov series are bit for bit
+    those of the same sweeps launched one kernel at a time (SU2_NO_GRAPH)."""
     import os
     dims, betas = [(6, 4, 10, 6), (4, 4, 4, 8)], [2.3, 2.6]
     out = []
@@ -193,6 +192,39 @@ def test_multi_sweep_graphs_match_direct_launches(su2, prec):
         assert np.array_equal(x, y)
     for x, y in zip(a[6], b[6]):
         assert np.array_equal(x, y)
+
+
+def test_series_batches_and_long_runs_match_direct_launches(su2):
+    """Graph forms that the short runs above do not reach, against direct
+    launches, bit for bit: a 32^4 binary32 run of 200 sweeps measured after
+    every sweep under block 64 (8192 plaquette tiles, so the per-sweep
+    partial slots, about 64 MiB at most, hold 84 sweeps: one run
+    graph with three series batches), and a 300-sweep run of two small
+    lattices measured every third sweep (longer than one run graph: graphs
+    of 16 sweeps and the binary remainder)."""
+    import os
+    cases = (([(32, 32, 32, 32)], [2.6], su2.F32, (64, 0, 3, 1), 200, 1),
+             ([(6, 4, 10, 6), (4, 4, 4, 8)], [2.3, 2.6], su2.F64, None, 300, 3))
+    for dims, betas, prec, launch, nsw, every in cases:
+        out = []
+        for direct in (False, True):
+            if direct:
+                os.environ["SU2_NO_GRAPH"] = "1"
+            try:
+                ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=17, prec=prec)
+                if launch:
+                    su2.su2_ensemble_set_launch(ens.h, *launch)
+                P, L = ens.run(nsw, 17, measure_every=every)
+                out.append((P, L, [ens.get_links(i) for i in range(len(dims))]))
+                ens.close()
+            finally:
+                os.environ.pop("SU2_NO_GRAPH", None)
+        (a, b) = out
+        print(dims[0], nsw, "sweeps:", a[0].shape, "measurements", flush=True)
+        assert a[0].shape == (len(dims), nsw // every)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        for x, y in zip(a[2], b[2]):
+            assert np.array_equal(x, y)
 
 
 @pytest.mark.parametrize("launch", [None, (128, 0, 2, 1)])
