@@ -45,15 +45,15 @@ INFINITY_CACHE_BYTES = 256 << 20
 # per lane; a grid of 0 counts as its effective size, one workgroup per
 # tile).  Valid only for the sources with this hash (the kernels and the host
 # code that orders their tiles).
-HB_TRAFFIC = {"sources_sha256": "0f9e12243cacaf6a7b46291161e8498bed0565d7b754d55ae6fd4918137b7fb9",
-              "by_launch": {(128, 4096, 3, 1): 74249637, (64, 8192, 3, 1): 74272729,
-                            (256, 2048, 3, 1): 74090744, (64, 8192, 1, 1): 78153193,
-                            (64, 4096, 3, 1): 74272987, (128, 2048, 3, 1): 74277195,
-                            (256, 1024, 3, 1): 74108357, (64, 7168, 3, 1): 76716103,
-                            (128, 3584, 3, 1): 77494977, (256, 1792, 3, 1): 76472175,
-                            (64, 4096, 3, 2): 75660387, (128, 2048, 3, 2): 75575508},
+HB_TRAFFIC = {"sources_sha256": "8ac6417eebde3bc20fd7f31e300ab26eae5f62d4bbda054a3e6ecffaf622b5d6",
+              "by_launch": {(128, 4096, 3, 1): 74249104, (64, 8192, 3, 1): 74273863,
+                            (256, 2048, 3, 1): 74094736, (64, 8192, 1, 1): 78245785,
+                            (64, 7168, 3, 1): 76533206, (128, 3584, 3, 1): 77228460,
+                            (256, 1792, 3, 1): 76072259, (64, 4096, 3, 1): 74261637,
+                            (128, 2048, 3, 1): 74268106, (256, 1024, 3, 1): 74100859,
+                            (64, 4096, 3, 2): 75724088, (128, 2048, 3, 2): 75571729},
               # the 64^4 control: 1 GiB algorithmic per launch
-              "control64": {(256, 32768, 0, 1): 1267400492}}
+              "control64": {(256, 32768, 0, 1): 1267011584}}
 KERNEL_SOURCES = ("su2_kernels.hip", "su2_device.hpp", "su2_internal.hpp", "su2_api.hip")
 
 

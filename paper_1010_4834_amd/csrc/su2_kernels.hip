@@ -767,11 +767,17 @@ __global__ void k_set_state(DevState *st, unsigned long long seed, unsigned swee
 // The same from the run state the host wrote into mapped host memory before
 // launching a captured run (words: seed low, seed high, sweep, run base), so
 // that the run's first node needs no kernel arguments of its own.
-__global__ void k_set_state_mapped(DevState *st, const volatile unsigned *src) {
-    st->seed = (unsigned long long)src[0] | ((unsigned long long)src[1] << 32);
-    st->sweep = src[2];
-    st->next = src[2];
-    st->run_base = src[3];
+// Run state from mapped host memory: src[0] the seed, src[1] the sweep word
+// (low half) and the run base (high half).  Two relaxed system-scope loads
+// are in flight together, one round trip to host memory (four dependent
+// volatile reads took four, ~8 us).
+__global__ void k_set_state_mapped(DevState *st, const unsigned long long *src) {
+    const unsigned long long seed = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned long long sr = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    st->seed = seed;
+    st->sweep = (unsigned)sr;
+    st->next = (unsigned)sr;
+    st->run_base = (unsigned)(sr >> 32);
 }
 
 __global__ void k_clear_err(DevState *st) { st->err = 0u; }
@@ -1179,7 +1185,7 @@ void launch_set_state(DevState *st, unsigned long long seed, unsigned sweep, uns
 }
 
 void launch_set_state_mapped(DevState *st, const unsigned *src, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_state_mapped, dim3(1), dim3(1), 0, s, st, src);
+    hipLaunchKernelGGL(k_set_state_mapped, dim3(1), dim3(1), 0, s, st, (const unsigned long long *)src);
 }
 
 void launch_clear_err(DevState *st, hipStream_t s) { hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(1), 0, s, st); }
