@@ -43,9 +43,9 @@ INFINITY_CACHE_BYTES = 256 << 20
 # the factors that make a 1 GiB device copy read back its own size; bytes
 # per launch for each launch shape measured (block, grid, tile mode, links
 # per lane; a grid of 0 counts as its effective size, one workgroup per
-# tile).  Valid only for the sources with this hash (the kernels and the host
-# code that orders their tiles).
-HB_TRAFFIC = {"sources_sha256": "8ac6417eebde3bc20fd7f31e300ab26eae5f62d4bbda054a3e6ecffaf622b5d6",
+# tile).  Valid only for the sources whose code (comments and layout aside)
+# has this hash: the kernels and the host code that orders their tiles.
+HB_TRAFFIC = {"sources_sha256": "f3d9d7bd90f0ae9b097c8e2a2b0890fce0f860495d8cef363ed0e4064d967e98",
               "by_launch": {(128, 4096, 3, 1): 74249104, (64, 8192, 3, 1): 74273863,
                             (256, 2048, 3, 1): 74094736, (64, 8192, 1, 1): 78245785,
                             (64, 7168, 3, 1): 76533206, (128, 3584, 3, 1): 77228460,
@@ -66,14 +66,25 @@ def effective_grid(grid, tiles):
     return full if grid <= 0 else min(grid, full)
 
 
+def code_only(text):
+    """C++ source text without its comments, whitespace runs collapsed to
+    one space (string and character literals kept as written)."""
+    import re
+    tok = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
+    text = tok.sub(lambda m: " " if m.group(0)[0] == "/" else m.group(0), text)
+    return " ".join(text.split())
+
+
 def kernel_sources_sha256():
-    """SHA-256 of the kernel sources, or None where they are not shipped."""
+    """SHA-256 of the code of the kernel sources (comments and layout
+    aside), or None where they are not shipped."""
     import hashlib
     h = hashlib.sha256()
     try:
         for f in KERNEL_SOURCES:
-            with open(os.path.join(ROOT, "paper_1010_4834_amd", "csrc", f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(ROOT, "paper_1010_4834_amd", "csrc", f), encoding="utf-8") as fh:
+                h.update(code_only(fh.read()).encode())
+                h.update(b"\0")
     except OSError:
         return None
     return h.hexdigest()

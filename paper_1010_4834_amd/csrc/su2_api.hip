@@ -1,6 +1,7 @@
 // su2_api.hip -- C ABI of the SU(2) library (include/su2.h): handles,
-// validation, device memory, tile tables, graph capture of one sweep,
-// per-kernel event timing, launch-shape autotuning and checkpoints.
+// validation, device memory, tile tables, graph capture of whole runs and
+// of sweep units, per-kernel event timing, launch-shape autotuning and
+// checkpoints.
 //
 // A lattice is an ensemble of one: every kernel walks the (lattice, tile)
 // list of its handle, so the batched and the single-lattice paths are the
@@ -31,11 +32,12 @@ using su2::Tile;
 
 namespace {
 
-// Sweeps per captured graph at most (SU2_GRAPH_SWEEPS overrides; 0 or 1
-// replays single-sweep graphs only).  Each graph launch leaves the GPU idle
-// for a few microseconds before its first kernel, so a run of n sweeps
-// replays as many graphs of this size as fit and then at most one graph of
-// each smaller power of two (20 sweeps: 16 + 4).
+// Sweeps per captured unit graph at most, for runs too long for one run
+// graph (SU2_GRAPH_SWEEPS overrides; 0 or 1 replays single-sweep graphs
+// only).  Each graph launch leaves the GPU idle for a few microseconds
+// before its first kernel, so such a run replays as many graphs of this
+// size as fit and then at most one graph of each smaller power of two
+// (300 sweeps: eighteen of 16, then 8 + 4).
 constexpr int GRAPH_SWEEPS_DEFAULT = 16;
 int graph_sweeps() {
     static const int n = [] {

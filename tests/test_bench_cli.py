@@ -65,3 +65,18 @@ def test_traffic_lookup_grid():
     for key in bench.HB_TRAFFIC["by_launch"]:
         block, grid, _, nl = key
         assert bench.effective_grid(grid, (32 ** 4 // 2) // (block * nl)) == grid
+
+
+def test_source_hash_ignores_comments_only():
+    """The traffic table is keyed by the code of the kernel sources: comments
+    and layout do not change the key, code (string literals included) does."""
+    sys.path.insert(0, ROOT)
+    import bench
+    a = 'int a = 1; // one\n/* two\n lines */ const char *s = "x // y";\n'
+    b = 'int   a = 1;\n\n const char *s = "x // y"; /* other */\n'
+    c = 'int a = 2; const char *s = "x // y";\n'
+    d = 'int a = 1; const char *s = "x /* y";\n'
+    assert bench.code_only(a) == bench.code_only(b) == 'int a = 1; const char *s = "x // y";'
+    assert bench.code_only(c) != bench.code_only(a)
+    assert bench.code_only(d) != bench.code_only(a)
+    assert bench.code_only("char q = '\"'; // \"\nint z;") == "char q = '\"'; int z;"
