@@ -104,6 +104,13 @@ def configs():
         "c2x4": dict(dims=[(32, 32, 32, 32)] * 4, betas=[2.6] * 4, seed=2, poly=False,
                      desc="4 independent replica chains of the 32^4 lattice (256 MiB of links, "
                           "the Infinity Cache's size) in one launch, 1 sweep + plaquette per step"),
+        # one GPU's share of the 32^4 lattice split into t-slabs over 2, 4 and
+        # 8 GPUs; a periodic 32^3 x Nt/g lattice stands in for the slab and its
+        # two ghost slices (same updates and reads per link, no exchange)
+        **{"slab%d" % g: dict(dims=[(32, 32, 32, 32 // g)], betas=[2.6], seed=2, poly=False,
+                              desc="32^3x%d SU(2) heat bath, beta=2.6, hot start, 1 sweep + plaquette "
+                                   "per step: one GPU's t-slab of the 32^4 lattice on %d GPUs" % (32 // g, g))
+           for g in (2, 4, 8)},
         "control64": dict(dims=[(64, 64, 64, 64)], betas=[2.6], seed=2, poly=False,
                           desc="64^4 SU(2) heat bath (1 GiB of links, beyond the 256 MB "
                                "Infinity Cache), beta=2.6, 1 sweep + plaquette per step"),

@@ -19,7 +19,9 @@ def test_workload_configs():
     sys.path.insert(0, ROOT)
     import bench
     cfg = bench.configs()
-    assert set(cfg) == {"c1", "c2", "c2x2", "c2x4", "c3", "c4", "c5", "control64"}
+    assert set(cfg) == {"c1", "c2", "c2x2", "c2x4", "c3", "c4", "c5", "control64", "slab2", "slab4", "slab8"}
+    for g in (2, 4, 8):
+        assert cfg["slab%d" % g]["dims"] == [(32, 32, 32, 32 // g)] and cfg["slab%d" % g]["betas"] == [2.6]
     for r in (2, 4):
         assert cfg["c2x%d" % r]["dims"] == [(32, 32, 32, 32)] * r and cfg["c2x%d" % r]["betas"] == [2.6] * r
     assert cfg["c2"]["dims"] == [(32, 32, 32, 32)] and cfg["c2"]["betas"] == [2.6]
