@@ -166,6 +166,34 @@ def test_full_size_c2_one_sweep(su2, orc, prec):
     lat.close()
 
 
+@pytest.mark.parametrize("prec", ["F32", "F64"])
+def test_try_recording_changes_nothing(su2, prec):
+    """The parity tests compare the kernels that record per-link try counts;
+    production runs use the forms without the record.  Both give bit for bit
+    the same links and series: 32^4 at beta = 2.6 under the benchmark's
+    autotuned shape, two measured sweeps (the fused-plaquette forms, and the
+    Polyakov kernel) and one unmeasured sweep."""
+    dims = (32, 32, 32, 32)
+    p = getattr(su2, prec)
+    shape, out = None, []
+    for record in (False, True):
+        ens = su2.Ensemble([dims], [2.6], start=su2.HOT, seed=2, prec=p)
+        if shape is None:
+            su2.su2_ensemble_autotune(ens.h)
+            shape = su2.su2_ensemble_get_launch(ens.h)
+            print("launch", shape, flush=True)
+        else:
+            su2.su2_ensemble_set_launch(ens.h, *shape)
+        ens.trace_tries(record)
+        P, L = ens.run(2, 2)
+        ens.run(1, 2, plaq=False, poly=False)
+        out.append((P, L, ens.get_links(0)))
+        ens.close()
+    (a, b) = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2])
+
+
 def test_launch_shapes_bitwise(su2, orc):
     """FP64 links do not depend on the launch shape, the tile mode (all four)
     or graph replay."""
