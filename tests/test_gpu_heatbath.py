@@ -136,6 +136,28 @@ def test_sweep_fp32(su2, orc, dims):
     lat.close()
 
 
+@pytest.mark.parametrize("beta", [0.0, 0.4, 1.0, 12.0])
+def test_sweep_fp32_coupling_range(su2, orc, beta):
+    """Binary32 sweeps across the sampler's regimes, from a random
+    configuration on the ragged lattice: beta = 0 (the uniform alpha = 0
+    draw), 0.4 and 1.0 (mostly Creutz, alpha < 2), 12 (Kennedy-Pendleton
+    far out in alpha, delta = 1 - a0 small)."""
+    dims = (6, 4, 10, 6)
+    V = int(np.prod(dims))
+    U0 = as_f32(inputs.random_config(dims, 36))
+    U = U0.copy()
+    lat = su2.Lattice(dims, start=su2.COLD, prec=su2.F32)
+    lat.set_links(U)
+    lat.trace_tries(True)
+    lat.heatbath(beta, 1, 8)
+    tr = np.zeros(4 * V, np.uint32)
+    orc.heatbath_sweep(dims, U, beta, 8, 0, ubits=23, trace=tr)
+    r = parity_util.check_fp32_sweep(orc, dims, beta, U0, lat.get_links(), U, lat.get_tries(), tr,
+                                     label=f"beta {beta:g} ")
+    assert r["flips"] <= max(2, V // 1000)
+    lat.close()
+
+
 @pytest.mark.parametrize("prec", ["F64", "F32"])
 def test_full_size_c2_one_sweep(su2, orc, prec):
     """32^4, beta = 2.6, hot start seed 2: one sweep at the benchmark shape."""
