@@ -69,6 +69,29 @@ def test_ape_and_wilson(su2, orc, dims):
         lat.close()
 
 
+@pytest.mark.parametrize("alpha,nsteps", [(0.0, 3), (1.0, 4), (0.7, 0)])
+def test_ape_weight_edges(su2, orc, alpha, nsteps):
+    """APE at the ends of its weight range and with no step: alpha = 0 keeps
+    every link, alpha = 1 keeps only the staple sum, nsteps = 0 gives the
+    raw spatial links; smeared links and smeared Wilson loops against the
+    oracle in binary64 and binary32."""
+    dims = (6, 4, 10, 6)
+    U = inputs.random_config(dims, 44)
+    U32 = U.astype(np.float32).astype(np.float64)
+    for prec, ref, tl, tw in ((su2.F64, U, 1e-12, 1e-13), (su2.F32, U32, 2e-5, 2e-5)):
+        lat = su2.Lattice(dims, start=su2.COLD, prec=prec)
+        lat.set_links(ref)
+        lat.ape_smear(alpha, nsteps)
+        S = lat.get_smeared()
+        So = orc.ape(dims, ref, alpha, nsteps)
+        assert np.abs(S - So).max() < tl, (prec, alpha, nsteps)
+        if alpha == 0.0 or nsteps == 0:
+            assert np.abs(S - ref[:, :3]).max() < (1e-15 if prec == su2.F64 else 1e-7)
+        W = lat.wilson_loops(4, 5)
+        assert np.abs(W - orc.wilson(dims, ref, 4, 5, So)).max() < tw
+        lat.close()
+
+
 @pytest.mark.parametrize("launch", [(64, 0, 1, 2), (128, 16, 0, 4), (192, 8, 1, 1), (256, 0, 1, 1), (64, 0, 3, 1)])
 def test_measurements_any_launch_shape(su2, orc, launch):
     """Plaquette, Polyakov loop, APE smearing and Wilson loops agree with the
