@@ -120,6 +120,8 @@ def test_measurements_any_launch_shape(su2, orc, launch):
     ((2, 2, 2, 16), 2, 12),   # column height 4 in binary32 (Nt divisible by 4, not 6)
     ((2, 2, 2, 4), 2, 3),     # the smallest time bound (T <= 4), below it; column height 4
     ((2, 4, 2, 6), 2, 4),     # the smallest time bound, at it; column height 6
+    ((2, 2, 2, 34), 2, 32),   # the largest time bound, T = 32 < Nt (column height 2)
+    ((2, 2, 2, 32), 2, 32),   # T = Nt = 32, a full wrap at the bound (column height 4)
 ])
 def test_wilson_columns_and_long_times(su2, orc, dims, Rm, Tm):
     """The trace kernel takes columns of sites along t and transports the
@@ -133,6 +135,19 @@ def test_wilson_columns_and_long_times(su2, orc, dims, Rm, Tm):
         W = lat.wilson_loops(Rm, Tm)
         assert np.abs(W - orc.wilson(dims, ref, Rm, Tm)).max() < tw, prec
         lat.close()
+
+
+def test_wilson_bounds_refused(su2):
+    """R beyond the smallest spatial extent, T beyond Nt or 32, and zero
+    bounds are EINVAL; nothing is launched."""
+    lat = su2.Lattice((4, 2, 6, 34), start=su2.COLD, prec=su2.F32)
+    for Rm, Tm in ((3, 2), (0, 2), (2, 0), (2, 33)):
+        with pytest.raises(su2.SU2Error) as e:
+            lat.wilson_loops(Rm, Tm)
+        assert e.value.status == su2.EINVAL, (Rm, Tm)
+    W = lat.wilson_loops(2, 32)
+    assert np.abs(np.asarray(W) - 1.0).max() < 1e-6   # cold start: every loop is 1
+    lat.close()
 
 
 def test_c4_full_size_sampled(su2, orc):
