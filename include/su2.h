@@ -278,9 +278,17 @@ su2_status su2_heatbath_noalloc(void *device_links, int Nx, int Ny, int Nz, int 
 /* ---- ensembles of independent lattices -------------------------------- */
 
 /* n independent lattices of uneven sizes and couplings that advance in the
- * same kernel launches (one workgroup walks a (lattice, tile) list).
- * dims: n*4 extents; betas: n couplings; lattice i uses lattice_id i in the
- * Philox counter; hot starts draw with `seed`. */
+ * same kernel launches (paper Sec. 2 heat bath and Sec. 4 chessboard on each
+ * lattice; one workgroup walks a (lattice, tile) list).  dims: n*4 extents
+ * (host, read during the call); betas: n couplings; lattice i uses
+ * lattice_id i in the Philox counter; hot starts draw with `seed`.  The
+ * lattices lie back to back in one link buffer: device_links, if not NULL,
+ * is a caller-owned device buffer of at least the sum of su2_link_bytes()
+ * over the lattices (device_bytes, else EINVAL), which the library uses
+ * but never frees.  EINVAL for n < 1 or n > 2^23, a NULL array, any
+ * lattice su2_create would refuse, more than 2^31 sites in all, or a beta
+ * < 0 or not finite; ENODEV without a GPU;
+ * EDEVICE or ENOMEM if device or pinned memory cannot be had. */
 su2_status su2_ensemble_create(int n, const int *dims, const double *betas, su2_start start,
                                uint64_t seed, su2_prec prec, void *device_links,
                                size_t device_bytes, su2_ensemble *out);
@@ -309,9 +317,13 @@ su2_status su2_ensemble_set_sampler(su2_ensemble ens, su2_sampler sampler);
 su2_status su2_ensemble_run(su2_ensemble ens, int nsweeps, int measure_every, uint64_t seed,
                             double *plaq, double *poly);
 /* Number of lattices, and the extents Nx, Ny, Nz, Nt of lattice i into
- * dims[0..3]: the series of su2_ensemble_run hold count*nsweeps values and
- * the link arrays of lattice i V_i*16.  EINVAL for a NULL pointer or i out
- * of range. */
+ * dims[0..3]: the series of su2_ensemble_run hold count*(nsweeps /
+ * measure_every) values and the link arrays of lattice i V_i*16.  EINVAL for
+ * a NULL pointer or i out of range.  The calls below act as their su2_*
+ * counterparts on lattice i (links in the canonical host layout, V_i*16
+ * float64; set rounds to binary32 for SU2_F32 and refuses non-unit links)
+ * or on the whole ensemble (statistics summed over the lattices; one launch
+ * shape, timing and try record for all of them). */
 su2_status su2_ensemble_count(su2_ensemble ens, int *n);
 su2_status su2_ensemble_get_dims(su2_ensemble ens, int i, int *dims);
 su2_status su2_ensemble_get_links(su2_ensemble ens, int i, double *host);
