@@ -108,11 +108,17 @@ size_t su2_link_bytes(int Nx, int Ny, int Nz, int Nt, su2_prec prec);
 su2_status su2_create(int Nx, int Ny, int Nz, int Nt, su2_start start, uint64_t seed,
                       su2_prec prec, void *device_links, size_t device_bytes,
                       su2_lattice *out);
+/* Waits for the handle's streams, then frees its device and pinned host
+ * memory and captured graphs; a caller-owned link buffer is left to the
+ * caller.  EINVAL for NULL. */
 su2_status su2_destroy(su2_lattice lat);
 
 /* Run later work on this HIP stream (a hipStream_t; NULL = the library's
  * own stream). */
 su2_status su2_set_stream(su2_lattice lat, void *hip_stream);
+/* Sampler of a0 for later heat-bath calls (SU2_HYBRID by default); EINVAL
+ * for other values.  It changes the draws, so a run that switches samplers
+ * is a different Markov chain. */
 su2_status su2_set_sampler(su2_lattice lat, su2_sampler sampler);
 
 /* nsweeps heat-bath sweeps (paper Sec. 2: each link drawn from
