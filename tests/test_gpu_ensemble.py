@@ -168,10 +168,11 @@ def test_measuring_does_not_change_the_chain(su2, prec):
 
 @pytest.mark.parametrize("prec", ["F64", "F32"])
 def test_multi_sweep_graphs_match_direct_launches(su2, prec):
-    """Runs of 21 sweeps, 5 sweeps and 37 sweeps measured every second sweep
-    (18 two-sweep units and one unmeasured sweep), each replayed as one
-    captured run graph; links, plaquette and Polyakov series are bit for bit
-    those of the same sweeps launched one kernel at a time (SU2_NO_GRAPH)."""
+    """Runs of 21 sweeps, 5 sweeps, 37 sweeps measured every second sweep
+    (18 two-sweep units and one unmeasured sweep) and 9 sweeps with another
+    seed, each replayed as one captured run graph; links, plaquette and
+    Polyakov series are bit for bit those of the same sweeps launched one
+    kernel at a time (SU2_NO_GRAPH)."""
     import os
     dims, betas = [(6, 4, 10, 6), (4, 4, 4, 8)], [2.3, 2.6]
     out = []
@@ -183,14 +184,15 @@ def test_multi_sweep_graphs_match_direct_launches(su2, prec):
             P, L = ens.run(21, 9)
             P2, L2 = ens.run(5, 9)     # the counter continues across runs
             P3, L3 = ens.run(37, 9, measure_every=2)
-            out.append((P, L, P2, L2, P3, L3, [ens.get_links(i) for i in range(len(dims))]))
+            P4, L4 = ens.run(9, 12)    # a new seed: the library uploads it before the run
+            out.append((P, L, P2, L2, P3, L3, P4, L4, [ens.get_links(i) for i in range(len(dims))]))
             ens.close()
         finally:
             os.environ.pop("SU2_NO_GRAPH", None)
     (a, b) = out
-    for x, y in zip(a[:6], b[:6]):
+    for x, y in zip(a[:8], b[:8]):
         assert np.array_equal(x, y)
-    for x, y in zip(a[6], b[6]):
+    for x, y in zip(a[8], b[8]):
         assert np.array_equal(x, y)
 
 
