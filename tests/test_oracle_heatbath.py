@@ -74,7 +74,7 @@ def chi2_delta(delta, alpha, nbins=40):
     return stats.chi2.sf(chi2, keep.sum() - 1)
 
 
-@pytest.mark.parametrize("alpha", [0.25, 1.0, 2.0, 6.0, 15.0])
+@pytest.mark.parametrize("alpha", [0.25, 1.0, 2.0, 6.0, 15.0, 60.0])
 @pytest.mark.parametrize("sampler", ["KP", "CREUTZ", "HYBRID"])
 def test_sampler_distribution(orc, alpha, sampler):
     if sampler == "KP" and alpha < 1:
