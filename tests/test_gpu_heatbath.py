@@ -263,6 +263,27 @@ def test_launch_shapes_bitwise_fp32(su2):
         assert np.array_equal(G, out[0])
 
 
+def test_launch_shapes_bitwise_full_size(su2):
+    """At 32^4 (4096 tiles of 128 half-sites) the benchmark's autotuner
+    candidates agree bit for bit: one link per lane in every tile mode, two
+    and four links per lane, two tiles per workgroup and the
+    occupancy-exact persistent grid; two sweeps from the binary32 hot
+    start."""
+    dims = (32, 32, 32, 32)
+    ref = None
+    for launch in ((128, 0, 3, 1), (64, 0, 1, 1), (256, 0, 2, 1), (128, 0, 0, 2), (64, 0, 3, 4),
+                   (128, 2048, 3, 1), (128, 3584, 3, 1)):
+        lat = su2.Lattice(dims, start=su2.HOT, seed=2, prec=su2.F32)
+        su2.su2_set_launch(lat.h, *launch)
+        lat.heatbath(2.6, 2, 2)
+        G = lat.get_links()
+        lat.close()
+        if ref is None:
+            ref = G
+        else:
+            assert np.array_equal(G, ref), launch
+
+
 def test_overrelax_fp64(su2, orc):
     dims = (6, 4, 4, 8)
     U = inputs.random_config(dims, 36)
