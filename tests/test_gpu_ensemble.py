@@ -229,6 +229,26 @@ def test_series_batches_and_long_runs_match_direct_launches(su2):
             assert np.array_equal(x, y)
 
 
+def test_ensemble_launch_shapes_bitwise_c5(su2):
+    """The 64 uneven lattices of C5 in binary32, two sweeps from the hot
+    start under launch shapes of every tile mode, links per lane 1, 2 and 4
+    and a persistent grid: every lattice's links agree bit for bit (lattice
+    boundaries fall inside workgroups and tiles differently in each)."""
+    dims, betas = inputs.c5_shapes()
+    ref = None
+    for launch in ((128, 0, 2, 1), (256, 0, 1, 1), (64, 0, 3, 2), (128, 0, 0, 4), (64, 2048, 1, 1)):
+        ens = su2.Ensemble(dims, betas, start=su2.HOT, seed=5, prec=su2.F32)
+        su2.su2_ensemble_set_launch(ens.h, *launch)
+        ens.run(2, 5, plaq=False, poly=False)
+        G = [ens.get_links(i) for i in range(len(dims))]
+        ens.close()
+        if ref is None:
+            ref = G
+        else:
+            for i in range(len(dims)):
+                assert np.array_equal(G[i], ref[i]), (launch, i)
+
+
 @pytest.mark.parametrize("launch", [None, (128, 0, 2, 1)])
 def test_ensemble_fp64_c3_shapes(su2, orc, launch):
     """The C3 beta scan at full size (16 x 32^3 x 4, beta in [2.1, 2.5], hot
