@@ -311,21 +311,59 @@ def test_overrelax_fp32(su2, orc):
     lat.set_links(U0)
     lat.overrelax(1)
     orc.overrelax_sweep(dims, O)
-    G = lat.get_links()
+    check_overrelax_fp32(orc, dims, U0, lat.get_links(), O)
+    lat.close()
+
+
+def check_overrelax_fp32(orc, dims, U0, G, O):
+    """Binary32 over-relaxed links G against the binary64 oracle's O, both
+    from U0: every link within 1e-5 or within its bound 2 E_V / k + 16u,
+    and at most one link in 10^5 plus five needing the bound."""
     err = np.abs(G - O).max(axis=2)
     par = parity_util.parity_array(dims)
     over = list(zip(*np.nonzero(err > 1e-5)))
+    masks = {}
     for s, mu in over:
         s, mu = int(s), int(mu)
-        before = np.where(parity_util.link_before_mask(par, mu, int(par[s]))[..., None], O, U0)
+        key = (mu, int(par[s]))
+        if key not in masks:
+            earlier = parity_util.link_before_mask(par, mu, key[1])
+            masks[key] = (earlier, np.where(earlier[..., None], O, U0))
+        earlier, before = masks[key]
         k = float(np.linalg.norm(orc.staple(dims, before, s, mu)))
-        earlier = parity_util.link_before_mask(par, mu, int(par[s]))
         ein = sum(float(np.linalg.norm(G[j, nu] - O[j, nu]))
                   for j, nu in parity_util.staple_link_ids(orc, dims, s, mu) if earlier[j, nu])
         bound = 2 * (parity_util.STAPLE_ROUNDING + ein) / k + 16 * parity_util.U32
         assert err[s, mu] <= bound, (s, mu, err[s, mu], bound)
     print(f"FP32 over-relaxation {dims}: max |dU| {err.max():.2e}, {len(over)} links > 1e-5 within their bound")
     assert len(over) <= err.size * 1e-5 + 5
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_overrelax_full_size(su2, orc, prec):
+    """One over-relaxation sweep at 32^4 under the benchmark's autotuned
+    launch shape against the oracle, from the configuration the benchmark
+    over-relaxes: the hot start (seed 2) after heat-bath sweeps at beta =
+    2.6 (on the GPU; both sides then start from its links).  Binary64 to
+    1e-12 per link with the plaquette unchanged; binary32 by the bound
+    above.  (From the Haar-random hot start itself about 0.08% of the
+    staples are small enough to need the bound.)"""
+    dims = (32, 32, 32, 32)
+    lat = su2.Lattice(dims, start=su2.HOT, seed=2, prec=getattr(su2, prec))
+    su2.su2_autotune(lat.h, 2.6)
+    print("launch", su2.su2_get_launch(lat.h), flush=True)
+    lat.heatbath(2.6, 5, 2)
+    U0 = lat.get_links()
+    O = U0.copy()
+    p0 = lat.plaquette()[0]
+    lat.overrelax(1)
+    orc.overrelax_sweep(dims, O)
+    G = lat.get_links()
+    if prec == "F64":
+        assert np.abs(G - O).max() < 1e-12
+        assert abs(lat.plaquette()[0] - p0) < 1e-13
+    else:
+        check_overrelax_fp32(orc, dims, U0, G, O)
     lat.close()
 
 
